@@ -1,0 +1,208 @@
+/*
+ * ara.h -- C-ABI of the MI355X (gfx950) Aggregate Risk Analysis library.
+ *
+ * Aggregate Risk Analysis (ARA) as defined in B. Varghese, "The GPU vs Phi
+ * Debate: Risk Analytics Using Many-Core Computing": a Year Event Table (YET,
+ * section 2.1 (i)) is run against a portfolio of layers, each covering a set
+ * of Event Loss Tables (ELT / extended XELT, sections 2.1 (ii) and 3.1) under
+ * occurrence and aggregate terms (section 2.1 (iii)); Algorithm 1 produces a
+ * Year Loss Table (YLT, section 2.3) from which PML and TVaR are taken.
+ * Secondary uncertainty (section 3) replaces each looked-up mean loss by a
+ * Beta-distributed draw.
+ *
+ * Conventions for every entry point
+ *  - Pointers named d_* are device pointers (memory of the context's GPU);
+ *    all others are host pointers.  Streams are hipStream_t passed as void*
+ *    (NULL = the null stream).
+ *  - Every call returns an ara_status (0 = ARA_OK, negative on error) and
+ *    never aborts; ara_last_error() gives a message for the last failure of
+ *    a context.  A context is not thread-safe: use one per host thread.
+ *  - Work is enqueued on the caller's stream; calls that return host values
+ *    (ara_load_yet, ara_load_portfolio, ara_pml_tvar, ara_sync_status)
+ *    synchronise that stream.
+ *  - The library allocates no large device memory: the YET is borrowed from
+ *    the caller, portfolio tables live in a caller-provided workspace, outputs
+ *    and scratch are caller buffers.  A context keeps a few hundred bytes of
+ *    device status words.
+ *
+ * Readings of points the paper leaves open (used identically by the tests'
+ * FP64 reference):
+ *  - ELT financial terms (section 2.2, Algorithm 1 "apply financial terms"):
+ *    l' = share * min(max(loss - retention, 0), limit).
+ *  - Occurrence terms on the event loss summed over a layer's ELTs; aggregate
+ *    terms on the running sum of occurrence losses (section 2.2), never fed
+ *    back into that sum.  The trial loss is the aggregate value after the
+ *    last occurrence.  Because occurrence losses are >= 0 and the aggregate
+ *    clamp is monotone, that value equals the clamp of the total, so the
+ *    device may sum a trial's occurrences in any order.
+ *  - Secondary uncertainty draws: Philox4x32-10 (Salmon et al., SC'11),
+ *    counter (k, i, elt_id, 0) for the independent uniform and (k, i, 0, 1)
+ *    for the correlated one, key (seed low 32 bits, seed high 32 bits), output
+ *    word 0 mapped to u = ((w >> 8) | 1) * 2^-24.  k = occurrence index in
+ *    the trial, i = absolute trial index.  sigma_C = 0 gives z = u_I and
+ *    sigma_I = 0 gives z = u_C exactly (section 3.2's extreme cases).
+ *  - Beta fit (section 3.3) with sigma = sigma_I + sigma_C; when
+ *    sigma/max_l >= sqrt(mu_b (1 - mu_b)) the cap uses (1 - 1e-6) times it.
+ *  - PML(RP) = k-th largest trial loss, TVaR(RP) = mean of the k largest,
+ *    k = max(1, floor(N / RP)).
+ */
+#ifndef ARA_H
+#define ARA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ara_status;
+
+enum {
+    ARA_OK = 0,
+    ARA_E_INVALID_ARG = -1,          /* a null/negative/inconsistent argument */
+    ARA_E_NO_DEVICE = -2,            /* the HIP device does not exist */
+    ARA_E_HIP = -3,                  /* a HIP runtime call failed (message has it) */
+    ARA_E_EVENT_ID_RANGE = -4,       /* an event id outside [0, n_catalogue) */
+    ARA_E_OFFSETS_NOT_MONOTONE = -5, /* YET trial offsets decrease or do not start at 0 */
+    ARA_E_TIMES_UNSORTED = -6,       /* time stamps decrease inside a trial */
+    ARA_E_BAD_ELT_ROW = -7,          /* NaN/negative value, mean >= max_loss with sigma > 0,
+                                        duplicate event in one ELT, share outside [0, 1],
+                                        negative retention */
+    ARA_E_WORKSPACE_TOO_SMALL = -8,  /* workspace / scratch smaller than required */
+    ARA_E_NUMERIC = -9,              /* a Beta quantile failed to converge */
+    ARA_E_UNSUPPORTED = -10          /* option combination not supported */
+};
+
+enum { ARA_SUM_NAIVE32 = 0, ARA_SUM_KAHAN32 = 1, ARA_SUM_F64 = 2 };
+enum { ARA_F32 = 0, ARA_F64 = 1 };
+
+typedef struct ara_context ara_context;
+typedef struct ara_yet ara_yet;
+typedef struct ara_portfolio ara_portfolio;
+
+/* One ELT / XELT (sections 2.1 (ii), 3.1).  Host arrays of n_rows entries,
+ * copied during ara_load_portfolio.  sigma_i, sigma_c and max_loss may be
+ * NULL (all zero; then the ELT has no secondary uncertainty). */
+typedef struct {
+    uint32_t elt_id;            /* caller's id; keys the random draws */
+    int32_t n_rows;
+    const int32_t *event_ids;   /* distinct, in [0, n_catalogue) */
+    const float *mean;          /* mean loss mu_l >= 0 */
+    const float *sigma_i;       /* independent standard deviation */
+    const float *sigma_c;       /* correlated standard deviation */
+    const float *max_loss;      /* exposure max_l > mean where sigma > 0 */
+    double retention, limit, share;   /* ELT financial terms (limit may be +inf) */
+} ara_elt_desc;
+
+/* One layer: its ELTs (in order) and the layer terms (section 2.1 (iii)). */
+typedef struct {
+    int32_t n_elts;
+    const ara_elt_desc *elts;
+    double occ_retention, occ_limit, agg_retention, agg_limit;   /* limits may be +inf */
+    uint32_t program_id;        /* label only */
+} ara_layer_desc;
+
+typedef struct {
+    int32_t n_layers;
+    const ara_layer_desc *layers;
+    uint64_t seed;              /* Philox key */
+    int32_t su_enabled;         /* 0: primary uncertainty only (mean losses) */
+} ara_portfolio_desc;
+
+typedef struct {
+    int64_t trial_begin;        /* first absolute trial of the run */
+    int64_t trial_count;        /* number of trials; -1 = to the end of the YET */
+    int32_t sum_mode;           /* ARA_SUM_*: how a trial's occurrence losses are summed */
+    int32_t ylt_dtype;          /* ARA_F32 or ARA_F64 for both YLT outputs */
+    float tail_band;            /* z or 1-z below this use the FP64 quantile; <= 0: 2^-20 */
+    int32_t reserved;
+    int64_t *d_hits;            /* optional [n_layers][trial_count]: non-zero lookups */
+    uint64_t *d_hit_chk;        /* optional [n_layers][trial_count]: sum over hits of
+                                   (k+1)*2654435761 + elt_id, modulo 2^64 */
+    void *d_scratch;            /* optional: ara_run_scratch_size() bytes of device scratch;
+                                   NULL = a buffer the context keeps (grown on demand) */
+    size_t scratch_bytes;
+} ara_run_opts;
+
+/* ---- context ------------------------------------------------------------ */
+ara_status ara_create(int hip_device, ara_context **out);
+void ara_destroy(ara_context *ctx);               /* frees outstanding handles too */
+const char *ara_status_string(ara_status s);
+const char *ara_last_error(const ara_context *ctx);
+
+/* ---- Year Event Table (section 2.1 (i)) ---------------------------------
+ * CSR by trial: trial t holds occurrences [d_trial_offsets[t],
+ * d_trial_offsets[t+1]) of d_event_ids (int32, 0-based catalogue ids) and
+ * d_times (float32 time stamps, may be NULL).  The arrays are borrowed and
+ * must stay alive and unchanged until ara_free_yet.  Validates on the device
+ * (ids in range, offsets[0] == 0 and non-decreasing, times non-decreasing
+ * inside each trial) and synchronises the stream. */
+ara_status ara_load_yet(ara_context *ctx, int64_t n_trials, int32_t n_catalogue,
+                        const int64_t *d_trial_offsets, const int32_t *d_event_ids,
+                        const float *d_times, void *stream, ara_yet **out);
+ara_status ara_free_yet(ara_context *ctx, ara_yet *yet);
+
+/* ---- portfolio (sections 2.1 (iii), 3.1, 3.3, 4.2) -----------------------
+ * ara_portfolio_workspace_size gives the bytes of device workspace that
+ * ara_load_portfolio needs for this description and catalogue size.
+ * ara_load_portfolio validates the rows, copies them into d_workspace and
+ * builds there, with device kernels, each layer's event-indexed direct-access
+ * structure and the per-row Beta fit; it synchronises the stream.  The
+ * workspace belongs to the portfolio until ara_free_portfolio; the host
+ * arrays of the description may be freed on return. */
+ara_status ara_portfolio_workspace_size(const ara_portfolio_desc *desc, int32_t n_catalogue,
+                                        size_t *bytes);
+ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
+                              int32_t n_catalogue, void *d_workspace, size_t bytes,
+                              void *stream, ara_portfolio **out);
+ara_status ara_free_portfolio(ara_context *ctx, ara_portfolio *pf);
+
+/* ---- the analysis (Algorithm 1 with secondary uncertainty) ---------------
+ * Runs trials [trial_begin, trial_begin + trial_count) and writes
+ * d_ylt_layers[l * trial_count + t] (loss of layer l in trial trial_begin+t)
+ * and d_ylt_portfolio[t] (sum over layers), in opts->ylt_dtype; either output
+ * may be NULL.  opts may be NULL (all trials, NAIVE32, F32).  Asynchronous:
+ * returns after enqueueing on the stream; a quantile failure is reported by
+ * ara_sync_status. */
+ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                   const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
+                   void *stream);
+
+/* Device scratch an ara_run over trial_count trials needs (the list of
+ * trials handed from the FP32 pass to the FP64-capable pass). */
+ara_status ara_run_scratch_size(int64_t trial_count, size_t *bytes);
+
+/* Synchronises the stream and reports ARA_E_NUMERIC (with the first failing
+ * trial, occurrence and elt_id in the message) if a run since the last call
+ * hit a non-converging quantile; clears the flag. */
+ara_status ara_sync_status(ara_context *ctx, void *stream);
+
+/* ---- risk metrics (section 2.3) -------------------------------------------
+ * PML and TVaR of the n losses in d_ylt (ARA_F32 or ARA_F64, all >= 0) for
+ * n_rp return periods; results to host arrays pml_out / tvar_out.  The k-th
+ * largest value is found by a device radix select over the bit patterns; the
+ * tail sum is accumulated in FP64.  d_scratch must hold
+ * ara_pml_tvar_scratch_size(n) bytes.  Synchronises the stream. */
+ara_status ara_pml_tvar_scratch_size(int64_t n, size_t *bytes);
+ara_status ara_pml_tvar(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, int64_t n,
+                        const double *return_periods, int32_t n_rp, double *pml_out,
+                        double *tvar_out, void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* ---- diagnostics (used by the tests) -------------------------------------
+ * ara_debug_philox: d_out[4j..4j+3] = Philox4x32-10(d_ctr[4j..4j+3], key).
+ * ara_debug_beta_quantile: d_x[j] = I^-1(z_j; a_j, b_j) by the same device
+ * code the analysis uses (FP32 bulk, FP64 in the tail band and for shapes the
+ * FP32 path does not cover), given z and its complement zc = 1 - z (FP64
+ * inputs, exact grid values) and a per-entry FP32 shape; d_path[j] (may be
+ * NULL) receives 0 for the FP32 path, 1 for the FP64 path. */
+ara_status ara_debug_philox(ara_context *ctx, int64_t n, const uint32_t *d_ctr, uint64_t key,
+                            uint32_t *d_out, void *stream);
+ara_status ara_debug_beta_quantile(ara_context *ctx, int64_t n, const float *d_a,
+                                   const float *d_b, const double *d_z, const double *d_zc,
+                                   float tail_band, float *d_x, int32_t *d_path, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARA_H */

@@ -1,0 +1,429 @@
+"""Python binding of the gfx950 ARA library (``libara.so``).
+
+The functions named ``ara_*`` mirror the C-ABI of ``include/ara.h`` one to one
+(argument marshalling only).  :class:`Ara` is a small convenience layer for
+the tests and the benchmark: it keeps device memory in torch tensors, passes
+their pointers and the current torch stream to the library, and checks every
+status.  Every computation runs in the library's HIP kernels; nothing here
+computes a loss or a risk metric.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libara.so")
+
+ARA_OK = 0
+ARA_E_INVALID_ARG = -1
+ARA_E_NO_DEVICE = -2
+ARA_E_HIP = -3
+ARA_E_EVENT_ID_RANGE = -4
+ARA_E_OFFSETS_NOT_MONOTONE = -5
+ARA_E_TIMES_UNSORTED = -6
+ARA_E_BAD_ELT_ROW = -7
+ARA_E_WORKSPACE_TOO_SMALL = -8
+ARA_E_NUMERIC = -9
+ARA_E_UNSUPPORTED = -10
+
+ARA_SUM_NAIVE32, ARA_SUM_KAHAN32, ARA_SUM_F64 = 0, 1, 2
+ARA_F32, ARA_F64 = 0, 1
+SUM_MODES = {"naive32": ARA_SUM_NAIVE32, "kahan32": ARA_SUM_KAHAN32, "f64": ARA_SUM_F64}
+
+EXPORTS = ["ara_create", "ara_destroy", "ara_status_string", "ara_last_error", "ara_load_yet",
+           "ara_free_yet", "ara_portfolio_workspace_size", "ara_load_portfolio",
+           "ara_free_portfolio", "ara_run", "ara_run_scratch_size", "ara_sync_status",
+           "ara_pml_tvar_scratch_size", "ara_pml_tvar", "ara_debug_philox",
+           "ara_debug_beta_quantile"]
+
+
+class AraError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class ara_elt_desc(C.Structure):
+    _fields_ = [("elt_id", C.c_uint32), ("n_rows", C.c_int32),
+                ("event_ids", C.c_void_p), ("mean", C.c_void_p), ("sigma_i", C.c_void_p),
+                ("sigma_c", C.c_void_p), ("max_loss", C.c_void_p),
+                ("retention", C.c_double), ("limit", C.c_double), ("share", C.c_double)]
+
+
+class ara_layer_desc(C.Structure):
+    _fields_ = [("n_elts", C.c_int32), ("elts", C.POINTER(ara_elt_desc)),
+                ("occ_retention", C.c_double), ("occ_limit", C.c_double),
+                ("agg_retention", C.c_double), ("agg_limit", C.c_double),
+                ("program_id", C.c_uint32)]
+
+
+class ara_portfolio_desc(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("layers", C.POINTER(ara_layer_desc)),
+                ("seed", C.c_uint64), ("su_enabled", C.c_int32)]
+
+
+class ara_run_opts(C.Structure):
+    _fields_ = [("trial_begin", C.c_int64), ("trial_count", C.c_int64),
+                ("sum_mode", C.c_int32), ("ylt_dtype", C.c_int32),
+                ("tail_band", C.c_float), ("reserved", C.c_int32),
+                ("d_hits", C.c_void_p), ("d_hit_chk", C.c_void_p),
+                ("d_scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libara.so``; fail loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+        L.ara_create.argtypes = [C.c_int, C.POINTER(p)]
+        L.ara_destroy.argtypes = [p]
+        L.ara_destroy.restype = None
+        L.ara_status_string.argtypes = [i32]
+        L.ara_status_string.restype = C.c_char_p
+        L.ara_last_error.argtypes = [p]
+        L.ara_last_error.restype = C.c_char_p
+        L.ara_load_yet.argtypes = [p, i64, i32, p, p, p, p, C.POINTER(p)]
+        L.ara_free_yet.argtypes = [p, p]
+        L.ara_portfolio_workspace_size.argtypes = [C.POINTER(ara_portfolio_desc), i32,
+                                                   C.POINTER(sz)]
+        L.ara_load_portfolio.argtypes = [p, C.POINTER(ara_portfolio_desc), i32, p, sz, p,
+                                         C.POINTER(p)]
+        L.ara_free_portfolio.argtypes = [p, p]
+        L.ara_run.argtypes = [p, p, p, C.POINTER(ara_run_opts), p, p, p]
+        L.ara_run_scratch_size.argtypes = [i64, C.POINTER(sz)]
+        L.ara_sync_status.argtypes = [p, p]
+        L.ara_pml_tvar_scratch_size.argtypes = [i64, C.POINTER(sz)]
+        L.ara_pml_tvar.argtypes = [p, p, i32, i64, p, i32, p, p, p, sz, p]
+        L.ara_debug_philox.argtypes = [p, i64, p, u64, p, p]
+        L.ara_debug_beta_quantile.argtypes = [p, i64, p, p, p, p, C.c_float, p, p, p]
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if f.restype is C.c_int:       # default
+                f.restype = i32
+        _lib = L
+    return _lib
+
+
+# ---- thin C-ABI mirrors ------------------------------------------------------
+def ara_create(device: int = 0):
+    h = C.c_void_p()
+    rc = lib().ara_create(int(device), C.byref(h))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_create: " + lib().ara_status_string(rc).decode())
+    return h
+
+
+def ara_destroy(ctx) -> None:
+    lib().ara_destroy(ctx)
+
+
+def ara_status_string(code: int) -> str:
+    return lib().ara_status_string(int(code)).decode()
+
+
+def ara_last_error(ctx) -> str:
+    return lib().ara_last_error(ctx).decode()
+
+
+def _check(ctx, rc: int, what: str):
+    if rc != ARA_OK:
+        raise AraError(rc, f"{what}: {ara_last_error(ctx)}")
+
+
+def ara_load_yet(ctx, n_trials: int, n_catalogue: int, d_offsets: int, d_event_ids: int,
+                 d_times: Optional[int], stream: Optional[int]):
+    h = C.c_void_p()
+    _check(ctx, lib().ara_load_yet(ctx, int(n_trials), int(n_catalogue), d_offsets, d_event_ids,
+                                   d_times, stream, C.byref(h)), "ara_load_yet")
+    return h
+
+
+def ara_free_yet(ctx, yet) -> None:
+    _check(ctx, lib().ara_free_yet(ctx, yet), "ara_free_yet")
+
+
+def ara_portfolio_workspace_size(desc: "ara_portfolio_desc", n_catalogue: int) -> int:
+    n = C.c_size_t()
+    rc = lib().ara_portfolio_workspace_size(C.byref(desc), int(n_catalogue), C.byref(n))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_portfolio_workspace_size: " + ara_status_string(rc))
+    return int(n.value)
+
+
+def ara_load_portfolio(ctx, desc: "ara_portfolio_desc", n_catalogue: int, d_workspace: int,
+                       nbytes: int, stream: Optional[int]):
+    h = C.c_void_p()
+    _check(ctx, lib().ara_load_portfolio(ctx, C.byref(desc), int(n_catalogue), d_workspace,
+                                         int(nbytes), stream, C.byref(h)), "ara_load_portfolio")
+    return h
+
+
+def ara_free_portfolio(ctx, pf) -> None:
+    _check(ctx, lib().ara_free_portfolio(ctx, pf), "ara_free_portfolio")
+
+
+def ara_run(ctx, yet, pf, opts: "ara_run_opts", d_ylt_layers: Optional[int],
+            d_ylt_portfolio: Optional[int], stream: Optional[int]) -> None:
+    _check(ctx, lib().ara_run(ctx, yet, pf, C.byref(opts), d_ylt_layers, d_ylt_portfolio, stream),
+           "ara_run")
+
+
+def ara_run_scratch_size(trial_count: int) -> int:
+    n = C.c_size_t()
+    rc = lib().ara_run_scratch_size(int(trial_count), C.byref(n))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_run_scratch_size")
+    return int(n.value)
+
+
+def ara_sync_status(ctx, stream: Optional[int]) -> None:
+    _check(ctx, lib().ara_sync_status(ctx, stream), "ara_run")
+
+
+def ara_pml_tvar_scratch_size(n: int) -> int:
+    sz = C.c_size_t()
+    rc = lib().ara_pml_tvar_scratch_size(int(n), C.byref(sz))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_pml_tvar_scratch_size")
+    return int(sz.value)
+
+
+def ara_pml_tvar(ctx, d_ylt: int, ylt_dtype: int, n: int, return_periods, d_scratch: int,
+                 scratch_bytes: int, stream: Optional[int]):
+    rp = np.ascontiguousarray(return_periods, np.float64)
+    pml = np.empty(rp.shape[0], np.float64)
+    tvar = np.empty(rp.shape[0], np.float64)
+    _check(ctx, lib().ara_pml_tvar(ctx, d_ylt, int(ylt_dtype), int(n), rp.ctypes.data,
+                                   rp.shape[0], pml.ctypes.data, tvar.ctypes.data, d_scratch,
+                                   int(scratch_bytes), stream), "ara_pml_tvar")
+    return pml, tvar
+
+
+def ara_debug_philox(ctx, n: int, d_ctr: int, key: int, d_out: int, stream: Optional[int]):
+    _check(ctx, lib().ara_debug_philox(ctx, int(n), d_ctr, int(key) & 0xFFFFFFFFFFFFFFFF, d_out,
+                                       stream), "ara_debug_philox")
+
+
+def ara_debug_beta_quantile(ctx, n: int, d_a: int, d_b: int, d_z: int, d_zc: int,
+                            tail_band: float, d_x: int, d_path: Optional[int],
+                            stream: Optional[int]):
+    _check(ctx, lib().ara_debug_beta_quantile(ctx, int(n), d_a, d_b, d_z, d_zc, float(tail_band),
+                                              d_x, d_path, stream), "ara_debug_beta_quantile")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) or None
+
+
+# ---- convenience layer -------------------------------------------------------
+class _Desc:
+    """Holds a portfolio description and the host arrays it points into."""
+
+    def __init__(self, pf):
+        self.keep = []
+        self.elt_arrays = []
+        layers = (ara_layer_desc * max(1, len(pf.layers)))()
+        for li, layer in enumerate(pf.layers):
+            elts = (ara_elt_desc * max(1, len(layer.elts)))()
+            self.elt_arrays.append(elts)
+            for j, e in enumerate(layer.elts):
+                ev = np.ascontiguousarray(e.event_ids, np.int32)
+                mu = np.ascontiguousarray(e.mean, np.float32)
+                si = np.ascontiguousarray(e.sigma_i, np.float32)
+                sc = np.ascontiguousarray(e.sigma_c, np.float32)
+                mx = np.ascontiguousarray(e.max_loss, np.float32)
+                self.keep += [ev, mu, si, sc, mx]
+                d = elts[j]
+                d.elt_id = int(e.elt_id) & 0xFFFFFFFF
+                d.n_rows = int(ev.shape[0])
+                d.event_ids, d.mean, d.sigma_i = ev.ctypes.data, mu.ctypes.data, si.ctypes.data
+                d.sigma_c, d.max_loss = sc.ctypes.data, mx.ctypes.data
+                d.retention, d.limit, d.share = float(e.retention), float(e.limit), float(e.share)
+            L = layers[li]
+            L.n_elts = len(layer.elts)
+            L.elts = C.cast(elts, C.POINTER(ara_elt_desc))
+            L.occ_retention, L.occ_limit = float(layer.occ_retention), float(layer.occ_limit)
+            L.agg_retention, L.agg_limit = float(layer.agg_retention), float(layer.agg_limit)
+            L.program_id = int(getattr(layer, "program_id", 0))
+        self.layers = layers
+        self.desc = ara_portfolio_desc(n_layers=len(pf.layers),
+                                       layers=C.cast(layers, C.POINTER(ara_layer_desc)),
+                                       seed=int(pf.seed) & 0xFFFFFFFFFFFFFFFF,
+                                       su_enabled=1 if pf.su_enabled else 0)
+
+
+class DeviceYET:
+    def __init__(self, handle, offsets, event_ids, times, n_trials, n_catalogue):
+        self.handle = handle
+        self.offsets, self.event_ids, self.times = offsets, event_ids, times
+        self.n_trials, self.n_catalogue = n_trials, n_catalogue
+
+
+class DevicePortfolio:
+    def __init__(self, handle, workspace, n_layers, n_elts, su):
+        self.handle = handle
+        self.workspace = workspace
+        self.n_layers, self.n_elts, self.su = n_layers, n_elts, su
+
+
+class Ara:
+    """One library context on ``cuda:device``; tensors are torch (HIP) tensors."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the ARA library needs a ROCm GPU (torch.cuda is not available)")
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.ctx = ara_create(device)
+
+    def close(self):
+        if self.ctx is not None:
+            ara_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- YET --------------------------------------------------------------------
+    def load_yet(self, yet, device_arrays=None, stream=None) -> DeviceYET:
+        """Copy a host YET (workloads.YET) to the device (or take already
+        resident tensors ``device_arrays=(offsets, event_ids, times)``) and
+        validate it with ``ara_load_yet``."""
+        t = self.torch
+        if device_arrays is None:
+            off = t.from_numpy(np.ascontiguousarray(yet.offsets, np.int64)).to(self.device)
+            ev = t.from_numpy(np.ascontiguousarray(yet.event_ids, np.int32)).to(self.device)
+            tm = (None if yet.times is None else
+                  t.from_numpy(np.ascontiguousarray(yet.times, np.float32)).to(self.device))
+        else:
+            off, ev, tm = device_arrays
+        n_trials = int(off.shape[0] - 1)
+        h = ara_load_yet(self.ctx, n_trials, int(yet.n_catalogue), _ptr(off), _ptr(ev), _ptr(tm),
+                         _stream_handle(stream))
+        return DeviceYET(h, off, ev, tm, n_trials, int(yet.n_catalogue))
+
+    def free_yet(self, y: DeviceYET):
+        ara_free_yet(self.ctx, y.handle)
+
+    # -- portfolio --------------------------------------------------------------
+    def workspace_size(self, pf, n_catalogue: int) -> int:
+        return ara_portfolio_workspace_size(_Desc(pf).desc, n_catalogue)
+
+    def load_portfolio(self, pf, n_catalogue: int, stream=None) -> DevicePortfolio:
+        d = _Desc(pf)
+        n = ara_portfolio_workspace_size(d.desc, n_catalogue)
+        ws = self.torch.empty(max(1, n), dtype=self.torch.uint8, device=self.device)
+        h = ara_load_portfolio(self.ctx, d.desc, n_catalogue, _ptr(ws), n, _stream_handle(stream))
+        return DevicePortfolio(h, ws, len(pf.layers), pf.n_elts, bool(pf.su_enabled))
+
+    def free_portfolio(self, p: DevicePortfolio):
+        ara_free_portfolio(self.ctx, p.handle)
+
+    # -- analysis ---------------------------------------------------------------
+    def run(self, y: DeviceYET, p: DevicePortfolio, trial_begin: int = 0,
+            trial_count: Optional[int] = None, sum_mode: str = "naive32",
+            ylt_dtype: str = "f32", tail_band: float = 0.0, diagnostics: bool = False,
+            out_layers=None, out_pf=None, stream=None, sync: bool = True,
+            layers: bool = True, scratch=None):
+        """``ara_run``; returns dict of device tensors ``ylt`` [n_layers, n]
+        and ``ylt_pf`` [n] (plus ``hits``/``hit_chk`` with diagnostics)."""
+        t = self.torch
+        if trial_count is None:
+            trial_count = y.n_trials - trial_begin
+        dt = t.float64 if ylt_dtype == "f64" else t.float32
+        if layers and out_layers is None:
+            out_layers = t.empty((p.n_layers, trial_count), dtype=dt, device=self.device)
+        if out_pf is None:
+            out_pf = t.empty(trial_count, dtype=dt, device=self.device)
+        hits = chk = None
+        if diagnostics:
+            hits = t.empty((p.n_layers, trial_count), dtype=t.int64, device=self.device)
+            chk = t.empty((p.n_layers, trial_count), dtype=t.int64, device=self.device)
+        o = ara_run_opts(trial_begin=int(trial_begin), trial_count=int(trial_count),
+                         sum_mode=SUM_MODES[sum_mode],
+                         ylt_dtype=ARA_F64 if ylt_dtype == "f64" else ARA_F32,
+                         tail_band=float(tail_band), reserved=0, d_hits=_ptr(hits),
+                         d_hit_chk=_ptr(chk), d_scratch=_ptr(scratch),
+                         scratch_bytes=0 if scratch is None else scratch.numel())
+        s = _stream_handle(stream)
+        ara_run(self.ctx, y.handle, p.handle, o, _ptr(out_layers), _ptr(out_pf), s)
+        if sync:
+            ara_sync_status(self.ctx, s)
+        res = {"ylt": out_layers, "ylt_pf": out_pf}
+        if diagnostics:
+            res["hits"], res["hit_chk"] = hits, chk
+        return res
+
+    def run_scratch_size(self, trial_count: int) -> int:
+        return ara_run_scratch_size(trial_count)
+
+    def pml_tvar(self, ylt, return_periods: Sequence[float], stream=None):
+        t = self.torch
+        n = int(ylt.numel())
+        sz = ara_pml_tvar_scratch_size(n)
+        scratch = t.empty(sz, dtype=t.uint8, device=self.device)
+        y = ylt.contiguous()
+        dtype = ARA_F64 if y.dtype == t.float64 else ARA_F32
+        return ara_pml_tvar(self.ctx, _ptr(y), dtype, n, return_periods, _ptr(scratch), sz,
+                            _stream_handle(stream))
+
+    # -- diagnostics ------------------------------------------------------------
+    def debug_philox(self, ctr, key: int, stream=None):
+        t = self.torch
+        c = t.as_tensor(np.ascontiguousarray(ctr, np.uint32).view(np.int32)).to(self.device)
+        out = t.empty_like(c)
+        ara_debug_philox(self.ctx, c.numel() // 4, _ptr(c), key, _ptr(out), _stream_handle(stream))
+        return out.cpu().numpy().view(np.uint32).reshape(-1, 4)
+
+    def debug_beta_quantile(self, a, b, z, zc, tail_band: float = 0.0, stream=None):
+        t = self.torch
+        A = t.as_tensor(np.ascontiguousarray(a, np.float32)).to(self.device)
+        B = t.as_tensor(np.ascontiguousarray(b, np.float32)).to(self.device)
+        Z = t.as_tensor(np.ascontiguousarray(z, np.float64)).to(self.device)
+        ZC = t.as_tensor(np.ascontiguousarray(zc, np.float64)).to(self.device)
+        x = t.empty(A.numel(), dtype=t.float32, device=self.device)
+        path = t.empty(A.numel(), dtype=t.int32, device=self.device)
+        ara_debug_beta_quantile(self.ctx, A.numel(), _ptr(A), _ptr(B), _ptr(Z), _ptr(ZC),
+                                tail_band, _ptr(x), _ptr(path), _stream_handle(stream))
+        return x.cpu().numpy(), path.cpu().numpy()
+
+
+def evaluations(yet, pf, trial_begin: int = 0, trial_count: Optional[int] = None) -> int:
+    """Trial x event x ELT evaluations of a run (zero lookups included)."""
+    if trial_count is None:
+        trial_count = yet.n_trials - trial_begin
+    occ = int(yet.offsets[trial_begin + trial_count] - yet.offsets[trial_begin])
+    return occ * sum(len(l.elts) for l in pf.layers)
+
+
+__all__ = [n for n in EXPORTS] + ["Ara", "AraError", "lib", "evaluations", "SUM_MODES"]

@@ -1,0 +1,591 @@
+// ara_api.hip -- host runtime behind the C-ABI of include/ara.h: contexts,
+// argument validation, the portfolio workspace layout, launches and error
+// reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "ara.h"
+#include "ara_internal.h"
+#include "ara_kernels.h"
+
+using namespace ara;
+
+struct ara_context {
+    int device = 0;
+    int n_cu = 0;
+    std::string last_error;
+    Status *d_status = nullptr;             // device status words
+    unsigned long long *d_maxlen = nullptr;
+    void *d_run_scratch = nullptr;          // grown on demand when ara_run gets no scratch
+    size_t run_scratch_bytes = 0;
+    std::set<ara_yet *> yets;
+    std::set<ara_portfolio *> pfs;
+};
+
+namespace {
+
+constexpr int kMaxRp = 256;
+constexpr float kDefaultTailBand = 9.5367431640625e-07f;   // 2^-20
+
+size_t run_scratch_need(int64_t trial_count) {
+    return 256 + ((size_t)(trial_count > 0 ? trial_count : 1) * sizeof(int32_t) + 255) / 256 * 256;
+}
+
+ara_status fail(ara_context *ctx, ara_status code, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+    }
+    return code;
+}
+
+#define ARA_HIP(ctx, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), ARA_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte layout of a portfolio workspace.
+struct Layout {
+    size_t layers, elts, evoff, rowq, row_mean, row_cfrac, row_meta, row_lnb, otab, raw, eltoff, dat,
+        total;
+    int64_t n_rows = 0;
+    int32_t n_elts = 0, max_layer_elts = 0;
+};
+
+ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, Layout *L) {
+    if (!d || n_cat <= 0 || d->n_layers < 0 || (d->n_layers > 0 && !d->layers))
+        return fail(ctx, ARA_E_INVALID_ARG, "bad portfolio description or catalogue size");
+    int64_t rows = 0;
+    int32_t ne = 0, mx = 0;
+    for (int l = 0; l < d->n_layers; ++l) {
+        const ara_layer_desc &ld = d->layers[l];
+        if (ld.n_elts < 0 || (ld.n_elts > 0 && !ld.elts) || ld.n_elts > 65535)
+            return fail(ctx, ARA_E_INVALID_ARG, "layer %d: bad ELT list", l);
+        if (!(ld.occ_retention >= 0) || !(ld.agg_retention >= 0) || !(ld.occ_limit >= 0) ||
+            !(ld.agg_limit >= 0) || std::isinf(ld.occ_retention) || std::isinf(ld.agg_retention))
+            return fail(ctx, ARA_E_BAD_ELT_ROW, "layer %d: terms must be finite retentions >= 0 "
+                                                "and limits >= 0", l);
+        for (int j = 0; j < ld.n_elts; ++j) {
+            const ara_elt_desc &e = ld.elts[j];
+            if (e.n_rows < 0 || (e.n_rows > 0 && (!e.event_ids || !e.mean)))
+                return fail(ctx, ARA_E_INVALID_ARG, "layer %d ELT %d: missing rows", l, j);
+            if (!(e.share >= 0.0 && e.share <= 1.0) || !(e.retention >= 0) ||
+                std::isinf(e.retention) || !(e.limit >= 0))
+                return fail(ctx, ARA_E_BAD_ELT_ROW, "layer %d ELT %d: share must be in [0,1], "
+                                                    "retention finite >= 0, limit >= 0", l, j);
+            rows += e.n_rows;
+        }
+        ne += ld.n_elts;
+        if (ld.n_elts > mx) mx = ld.n_elts;
+    }
+    if (rows >= ((int64_t)1 << 32) - 1)
+        return fail(ctx, ARA_E_UNSUPPORTED, "more than 2^32 ELT rows in one portfolio");
+    L->n_rows = rows;
+    L->n_elts = ne;
+    L->max_layer_elts = mx;
+    const int64_t nl = d->n_layers;
+    size_t o = 0;
+    L->layers = o; o += align256(sizeof(LayerDev) * (nl ? nl : 1));
+    L->elts = o; o += align256(sizeof(EltDev) * (ne ? ne : 1));
+    L->evoff = o; o += align256(sizeof(uint32_t) * (size_t)nl * ((size_t)n_cat + 1));
+    L->rowq = o; o += align256(sizeof(RowQ) * (size_t)(rows ? rows : 1));
+    L->row_mean = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
+    L->row_cfrac = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
+    L->row_meta = o; o += align256(sizeof(uint32_t) * (size_t)(rows ? rows : 1));
+    L->row_lnb = o; o += align256(sizeof(double) * (size_t)(rows ? rows : 1));
+    L->otab = o; o += d->su_enabled ? 0 : align256(sizeof(float) * (size_t)nl * n_cat);
+    L->raw = o; o += align256(sizeof(RawRow) * (size_t)(rows ? rows : 1));
+    L->eltoff = o; o += align256(sizeof(int64_t) * (size_t)(ne + 1));
+    L->dat = o; o += align256(sizeof(int32_t) * (size_t)(mx ? mx : 1) * n_cat);
+    L->total = o;
+    return ARA_OK;
+}
+
+ara_status check_status(ara_context *ctx, hipStream_t s, const char *what) {
+    Status h;
+    ARA_HIP(ctx, hipMemcpyAsync(&h, ctx->d_status, sizeof h, hipMemcpyDeviceToHost, s));
+    ARA_HIP(ctx, hipStreamSynchronize(s));
+    if (h.code == 0) return ARA_OK;
+    ARA_HIP(ctx, hipMemsetAsync(ctx->d_status, 0, sizeof(Status), s));
+    ARA_HIP(ctx, hipStreamSynchronize(s));
+    switch (h.code) {
+    case ARA_E_EVENT_ID_RANGE:
+        return fail(ctx, h.code, "%s: event id %lld out of range (trial %lld, position %lld)", what,
+                    (long long)h.where[2], (long long)h.where[0], (long long)h.where[1]);
+    case ARA_E_OFFSETS_NOT_MONOTONE:
+        return fail(ctx, h.code, "%s: trial offsets not monotone at trial %lld", what,
+                    (long long)h.where[0]);
+    case ARA_E_TIMES_UNSORTED:
+        return fail(ctx, h.code, "%s: time stamps decrease in trial %lld at occurrence %lld", what,
+                    (long long)h.where[0], (long long)h.where[1]);
+    case ARA_E_BAD_ELT_ROW:
+        return fail(ctx, h.code, "%s: bad ELT row %lld%s", what, (long long)h.where[1],
+                    h.where[0] == -2 ? " (duplicate event in one ELT)" : "");
+    case ARA_E_NUMERIC:
+        return fail(ctx, h.code, "%s: Beta quantile did not converge (trial %lld, occurrence %lld, "
+                                 "elt_id %lld)", what, (long long)h.where[0], (long long)h.where[1],
+                    (long long)h.where[2]);
+    default:
+        return fail(ctx, h.code, "%s: device reported status %d", what, h.code);
+    }
+}
+
+float to_f32_term(double v) { return std::isinf(v) ? INFINITY : (float)v; }
+
+}  // namespace
+
+extern "C" {
+
+const char *ara_status_string(ara_status s) {
+    switch (s) {
+    case ARA_OK: return "ok";
+    case ARA_E_INVALID_ARG: return "invalid argument";
+    case ARA_E_NO_DEVICE: return "no such device";
+    case ARA_E_HIP: return "HIP runtime error";
+    case ARA_E_EVENT_ID_RANGE: return "event id out of range";
+    case ARA_E_OFFSETS_NOT_MONOTONE: return "trial offsets not monotone";
+    case ARA_E_TIMES_UNSORTED: return "time stamps unsorted";
+    case ARA_E_BAD_ELT_ROW: return "bad ELT row";
+    case ARA_E_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case ARA_E_NUMERIC: return "numeric failure";
+    case ARA_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *ara_last_error(const ara_context *ctx) {
+    return ctx ? ctx->last_error.c_str() : "no context";
+}
+
+ara_status ara_create(int hip_device, ara_context **out) {
+    if (!out) return ARA_E_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n)
+        return ARA_E_NO_DEVICE;
+    ara_context *ctx = new ara_context();
+    ctx->device = hip_device;
+    hipDeviceProp_t prop;
+    if (hipSetDevice(hip_device) != hipSuccess ||
+        hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+        delete ctx;
+        return ARA_E_HIP;
+    }
+    ctx->n_cu = prop.multiProcessorCount;
+    if (hipMalloc((void **)&ctx->d_status, sizeof(Status)) != hipSuccess ||
+        hipMalloc((void **)&ctx->d_maxlen, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(ctx->d_status, 0, sizeof(Status)) != hipSuccess) {
+        (void)hipFree(ctx->d_status);
+        delete ctx;
+        return ARA_E_HIP;
+    }
+    *out = ctx;
+    return ARA_OK;
+}
+
+void ara_destroy(ara_context *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (ara_yet *y : ctx->yets) delete y;
+    for (ara_portfolio *p : ctx->pfs) {
+        delete[] p->h_layers;
+        delete p;
+    }
+    (void)hipFree(ctx->d_status);
+    (void)hipFree(ctx->d_maxlen);
+    (void)hipFree(ctx->d_run_scratch);
+    delete ctx;
+}
+
+ara_status ara_load_yet(ara_context *ctx, int64_t n_trials, int32_t n_catalogue,
+                        const int64_t *d_trial_offsets, const int32_t *d_event_ids,
+                        const float *d_times, void *stream, ara_yet **out) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!out || n_trials < 0 || n_catalogue <= 0 || !d_trial_offsets ||
+        (n_trials > 0 && !d_event_ids) || n_trials > (int64_t)0xffffffff)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_load_yet: bad arguments");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    ARA_HIP(ctx, hipMemsetAsync(ctx->d_status, 0, sizeof(Status), s));
+    ARA_HIP(ctx, hipMemsetAsync(ctx->d_maxlen, 0, sizeof(unsigned long long), s));
+    int64_t n_occ = 0;
+    ARA_HIP(ctx, hipMemcpyAsync(&n_occ, d_trial_offsets + n_trials, sizeof n_occ,
+                                hipMemcpyDeviceToHost, s));
+    if (n_trials > 0)
+        ARA_HIP(ctx, launch_validate_yet(d_trial_offsets, d_event_ids, d_times, n_trials,
+                                         n_catalogue, ctx->d_status, ctx->d_maxlen, s));
+    unsigned long long maxlen = 0;
+    ARA_HIP(ctx, hipMemcpyAsync(&maxlen, ctx->d_maxlen, sizeof maxlen, hipMemcpyDeviceToHost, s));
+    ara_status st = check_status(ctx, s, "ara_load_yet");
+    if (st != ARA_OK) return st;
+    if (maxlen > 0xffffffffull)
+        return fail(ctx, ARA_E_UNSUPPORTED, "ara_load_yet: a trial has >= 2^32 occurrences");
+    ara_yet *y = new ara_yet();
+    y->ctx = ctx;
+    y->n_trials = n_trials;
+    y->n_catalogue = n_catalogue;
+    y->d_off = d_trial_offsets;
+    y->d_ev = d_event_ids;
+    y->d_times = d_times;
+    y->n_occ = n_occ;
+    y->max_trial_len = (int64_t)maxlen;
+    ctx->yets.insert(y);
+    *out = y;
+    return ARA_OK;
+}
+
+ara_status ara_free_yet(ara_context *ctx, ara_yet *yet) {
+    if (!ctx || !yet || !ctx->yets.count(yet)) return ARA_E_INVALID_ARG;
+    ctx->yets.erase(yet);
+    delete yet;
+    return ARA_OK;
+}
+
+ara_status ara_portfolio_workspace_size(const ara_portfolio_desc *desc, int32_t n_catalogue,
+                                        size_t *bytes) {
+    if (!bytes) return ARA_E_INVALID_ARG;
+    Layout L;
+    ara_status st = plan(nullptr, desc, n_catalogue, &L);
+    if (st != ARA_OK) return st;
+    *bytes = L.total;
+    return ARA_OK;
+}
+
+ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
+                              int32_t n_catalogue, void *d_workspace, size_t bytes, void *stream,
+                              ara_portfolio **out) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!out) return fail(ctx, ARA_E_INVALID_ARG, "ara_load_portfolio: null out");
+    *out = nullptr;
+    Layout L;
+    ara_status st = plan(ctx, desc, n_catalogue, &L);
+    if (st != ARA_OK) return st;
+    if (!d_workspace || bytes < L.total)
+        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_load_portfolio: need %zu bytes, got %zu",
+                    L.total, bytes);
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    char *w = (char *)d_workspace;
+
+    // host staging: layer and ELT records, raw rows grouped by ELT
+    const int nl = desc->n_layers;
+    std::vector<LayerDev> hl(nl > 0 ? nl : 1);
+    std::vector<EltDev> he(L.n_elts > 0 ? L.n_elts : 1);
+    std::vector<RawRow> raw((size_t)(L.n_rows > 0 ? L.n_rows : 1));
+    std::vector<int64_t> eltoff((size_t)L.n_elts + 1, 0);
+    int32_t ei = 0;
+    int64_t ri = 0;
+    for (int l = 0; l < nl; ++l) {
+        const ara_layer_desc &ld = desc->layers[l];
+        LayerDev &D = hl[l];
+        std::memset(&D, 0, sizeof D);
+        D.occ_r = to_f32_term(ld.occ_retention);
+        D.occ_l = to_f32_term(ld.occ_limit);
+        D.agg_r = to_f32_term(ld.agg_retention);
+        D.agg_l = to_f32_term(ld.agg_limit);
+        D.elt_begin = ei;
+        D.n_elts = ld.n_elts;
+        D.row_base = ri;
+        D.evoff_base = (int64_t)l * ((int64_t)n_catalogue + 1);
+        D.otab_base = desc->su_enabled ? -1 : (int64_t)l * n_catalogue;
+        D.flags = 0;
+        for (int j = 0; j < ld.n_elts; ++j, ++ei) {
+            const ara_elt_desc &e = ld.elts[j];
+            he[ei].elt_id = e.elt_id;
+            he[ei].retention = to_f32_term(e.retention);
+            he[ei].limit = to_f32_term(e.limit);
+            he[ei].share = (float)e.share;
+            for (int r = 0; r < e.n_rows; ++r, ++ri) {
+                RawRow &R = raw[(size_t)ri];
+                R.event = e.event_ids[r];
+                R.mean = e.mean[r];
+                R.sigma_i = e.sigma_i ? e.sigma_i[r] : 0.0f;
+                R.sigma_c = e.sigma_c ? e.sigma_c[r] : 0.0f;
+                R.max_loss = e.max_loss ? e.max_loss[r] : INFINITY;
+            }
+            eltoff[(size_t)ei + 1] = ri;
+        }
+        D.n_rows = (int32_t)(ri - D.row_base);
+    }
+
+    ara_portfolio *p = new ara_portfolio();
+    p->ctx = ctx;
+    p->n_catalogue = n_catalogue;
+    p->n_layers = nl;
+    p->n_elts = L.n_elts;
+    p->n_rows = L.n_rows;
+    p->seed = desc->seed;
+    p->su_enabled = desc->su_enabled ? 1 : 0;
+    p->max_layer_elts = L.max_layer_elts;
+    p->d_layers = (LayerDev *)(w + L.layers);
+    p->d_elts = (EltDev *)(w + L.elts);
+    p->d_evoff = (uint32_t *)(w + L.evoff);
+    p->d_rowq = (RowQ *)(w + L.rowq);
+    p->d_row_mean = (float *)(w + L.row_mean);
+    p->d_row_cfrac = (float *)(w + L.row_cfrac);
+    p->d_row_meta = (uint32_t *)(w + L.row_meta);
+    p->d_row_lnb = (double *)(w + L.row_lnb);
+    p->d_otab = desc->su_enabled ? nullptr : (float *)(w + L.otab);
+    p->d_workspace = d_workspace;
+    p->workspace_bytes = bytes;
+    RawRow *d_raw = (RawRow *)(w + L.raw);
+    int64_t *d_eltoff = (int64_t *)(w + L.eltoff);
+    int32_t *d_dat = (int32_t *)(w + L.dat);
+
+    auto cleanup = [&](ara_status code) {
+        delete p;
+        return code;
+    };
+#define ARA_HIP_P(call)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return cleanup(fail(ctx, ARA_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_))); \
+    } while (0)
+
+    ARA_HIP_P(hipMemsetAsync(ctx->d_status, 0, sizeof(Status), s));
+    if (nl > 0)
+        ARA_HIP_P(hipMemcpyAsync(p->d_layers, hl.data(), sizeof(LayerDev) * nl,
+                                 hipMemcpyHostToDevice, s));
+    if (L.n_elts > 0)
+        ARA_HIP_P(hipMemcpyAsync(p->d_elts, he.data(), sizeof(EltDev) * L.n_elts,
+                                 hipMemcpyHostToDevice, s));
+    if (L.n_rows > 0)
+        ARA_HIP_P(hipMemcpyAsync(d_raw, raw.data(), sizeof(RawRow) * (size_t)L.n_rows,
+                                 hipMemcpyHostToDevice, s));
+    ARA_HIP_P(hipMemcpyAsync(d_eltoff, eltoff.data(), sizeof(int64_t) * eltoff.size(),
+                             hipMemcpyHostToDevice, s));
+    ARA_HIP_P(launch_check_rows(d_raw, L.n_rows, n_catalogue, p->su_enabled, ctx->d_status, s));
+    {
+        ara_status cs = check_status(ctx, s, "ara_load_portfolio");
+        if (cs != ARA_OK) return cleanup(cs);
+    }
+    for (int l = 0; l < nl; ++l) {
+        ARA_HIP_P(launch_build_layer(d_raw, d_eltoff, p->d_elts, p->d_layers + l, hl[l], n_catalogue,
+                                     p->su_enabled, d_dat, p->d_evoff, p->d_rowq, p->d_row_mean,
+                                     p->d_row_cfrac, p->d_row_meta, p->d_row_lnb, p->d_otab,
+                                     ctx->d_status, s));
+    }
+    p->h_layers = new LayerDev[nl > 0 ? nl : 1];
+    if (nl > 0)
+        ARA_HIP_P(hipMemcpyAsync(p->h_layers, p->d_layers, sizeof(LayerDev) * nl,
+                                 hipMemcpyDeviceToHost, s));
+    {
+        ara_status cs = check_status(ctx, s, "ara_load_portfolio");
+        if (cs != ARA_OK) {
+            delete[] p->h_layers;
+            return cleanup(cs);
+        }
+    }
+#undef ARA_HIP_P
+    p->all_flags = 0;
+    for (int l = 0; l < nl; ++l) p->all_flags |= p->h_layers[l].flags;
+    ctx->pfs.insert(p);
+    *out = p;
+    return ARA_OK;
+}
+
+ara_status ara_free_portfolio(ara_context *ctx, ara_portfolio *pf) {
+    if (!ctx || !pf || !ctx->pfs.count(pf)) return ARA_E_INVALID_ARG;
+    ctx->pfs.erase(pf);
+    delete[] pf->h_layers;
+    delete pf;
+    return ARA_OK;
+}
+
+ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                   const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
+                   void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!yet || !pf || !ctx->yets.count(const_cast<ara_yet *>(yet)) ||
+        !ctx->pfs.count(const_cast<ara_portfolio *>(pf)))
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run: unknown YET or portfolio handle");
+    if (yet->n_catalogue != pf->n_catalogue)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run: YET catalogue %d != portfolio catalogue %d",
+                    yet->n_catalogue, pf->n_catalogue);
+    ara_run_opts o;
+    std::memset(&o, 0, sizeof o);
+    o.trial_count = -1;
+    if (opts) o = *opts;
+    if (o.trial_count < 0) o.trial_count = yet->n_trials - o.trial_begin;
+    if (o.trial_begin < 0 || o.trial_count < 0 || o.trial_begin + o.trial_count > yet->n_trials)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run: trial range [%lld, +%lld) outside the YET",
+                    (long long)o.trial_begin, (long long)o.trial_count);
+    if (o.sum_mode < ARA_SUM_NAIVE32 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
+        o.ylt_dtype > ARA_F64)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run: bad sum_mode or ylt_dtype");
+    if (o.trial_count > 0x7fffffff)
+        return fail(ctx, ARA_E_UNSUPPORTED, "ara_run: more than 2^31 trials in one run");
+    if (!(o.tail_band > 0.0f)) o.tail_band = kDefaultTailBand;
+    if (o.trial_count == 0 || pf->n_layers == 0) {
+        hipStream_t s = (hipStream_t)stream;
+        const size_t es = o.ylt_dtype == ARA_F64 ? 8 : 4;
+        ARA_HIP(ctx, hipSetDevice(ctx->device));
+        if (d_ylt_portfolio && o.trial_count > 0)
+            ARA_HIP(ctx, hipMemsetAsync(d_ylt_portfolio, 0, es * o.trial_count, s));
+        return ARA_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    const bool f64out = o.ylt_dtype == ARA_F64;
+    if (!pf->su_enabled) {
+        if (o.d_hits || o.d_hit_chk)
+            return fail(ctx, ARA_E_UNSUPPORTED,
+                        "ara_run: hit diagnostics need a portfolio with secondary uncertainty");
+        for (int l = 0; l < pf->n_layers; ++l) {
+            PuLaunch p;
+            p.off = yet->d_off;
+            p.ev = yet->d_ev;
+            p.trial_begin = o.trial_begin;
+            p.trial_count = o.trial_count;
+            p.otab = pf->d_otab + (int64_t)l * pf->n_catalogue;
+            p.n_cat = pf->n_catalogue;
+            p.agg_r = pf->h_layers[l].agg_r;
+            p.agg_l = pf->h_layers[l].agg_l;
+            p.layer = l;
+            p.ylt_layers = d_ylt_layers;
+            p.ylt_pf = d_ylt_portfolio;
+            p.accumulate_pf = l > 0;
+            int64_t waves = (o.trial_count + 3) / 4;
+            int64_t g = waves < (int64_t)ctx->n_cu * 8 ? waves : (int64_t)ctx->n_cu * 8;
+            p.grid = (int)(g < 1 ? 1 : g);
+            ARA_HIP(ctx, launch_pu(p, o.sum_mode, f64out, s));
+        }
+        return ARA_OK;
+    }
+    SuLaunch p;
+    p.off = yet->d_off;
+    p.ev = yet->d_ev;
+    p.trial_begin = o.trial_begin;
+    p.trial_count = o.trial_count;
+    p.layers = pf->d_layers;
+    p.n_layers = pf->n_layers;
+    p.elts = pf->d_elts;
+    p.evoff = pf->d_evoff;
+    p.rowq = pf->d_rowq;
+    p.row_mean = pf->d_row_mean;
+    p.row_cfrac = pf->d_row_cfrac;
+    p.row_meta = pf->d_row_meta;
+    p.row_lnb = pf->d_row_lnb;
+    p.seed = pf->seed;
+    p.tail_band = o.tail_band;
+    p.ylt_layers = d_ylt_layers;
+    p.ylt_pf = d_ylt_portfolio;
+    p.hits = o.d_hits;
+    p.hit_chk = o.d_hit_chk;
+    p.status = ctx->d_status;
+    const size_t need = run_scratch_need(o.trial_count);
+    char *scr = (char *)o.d_scratch;
+    if (scr) {
+        if (o.scratch_bytes < need)
+            return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_run: need %zu scratch bytes", need);
+    } else {
+        if (ctx->run_scratch_bytes < need) {
+            ARA_HIP(ctx, hipStreamSynchronize(s));
+            ARA_HIP(ctx, hipFree(ctx->d_run_scratch));
+            ctx->d_run_scratch = nullptr;
+            ctx->run_scratch_bytes = 0;
+            ARA_HIP(ctx, hipMalloc(&ctx->d_run_scratch, need));
+            ctx->run_scratch_bytes = need;
+        }
+        scr = (char *)ctx->d_run_scratch;
+    }
+    p.redo_count = (uint32_t *)scr;
+    p.redo = (int32_t *)(scr + 256);
+    p.redo_grid = ctx->n_cu * 4;
+    ARA_HIP(ctx, launch_su(p, o.sum_mode, f64out, s));
+    return ARA_OK;
+}
+
+ara_status ara_run_scratch_size(int64_t trial_count, size_t *bytes) {
+    if (!bytes || trial_count < 0) return ARA_E_INVALID_ARG;
+    *bytes = run_scratch_need(trial_count);
+    return ARA_OK;
+}
+
+ara_status ara_sync_status(ara_context *ctx, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    return check_status(ctx, (hipStream_t)stream, "ara_run");
+}
+
+ara_status ara_pml_tvar_scratch_size(int64_t n, size_t *bytes) {
+    if (!bytes || n < 0) return ARA_E_INVALID_ARG;
+    *bytes = align256(pml_scratch_bytes(n)) + align256(sizeof(double) * 2 * kMaxRp);
+    return ARA_OK;
+}
+
+ara_status ara_pml_tvar(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, int64_t n,
+                        const double *return_periods, int32_t n_rp, double *pml_out,
+                        double *tvar_out, void *d_scratch, size_t scratch_bytes, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!d_ylt || n <= 0 || !return_periods || n_rp <= 0 || n_rp > kMaxRp || !pml_out ||
+        !tvar_out || (ylt_dtype != ARA_F32 && ylt_dtype != ARA_F64))
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_pml_tvar: bad arguments");
+    size_t need = 0;
+    ara_pml_tvar_scratch_size(n, &need);
+    if (!d_scratch || scratch_bytes < need)
+        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_pml_tvar: need %zu scratch bytes", need);
+    std::vector<int64_t> ks(n_rp);
+    for (int r = 0; r < n_rp; ++r) {
+        const double rp = return_periods[r];
+        if (!(rp > 0.0)) return fail(ctx, ARA_E_INVALID_ARG, "ara_pml_tvar: return period <= 0");
+        double kk = std::floor((double)n / rp);
+        int64_t k = kk < 1.0 ? 1 : (kk > (double)n ? n : (int64_t)kk);
+        ks[r] = k;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    double *d_out = (double *)((char *)d_scratch + align256(pml_scratch_bytes(n)));
+    ARA_HIP(ctx, launch_pml_tvar(d_ylt, ylt_dtype, n, ks.data(), n_rp, d_scratch, d_out, s));
+    std::vector<double> h(2 * (size_t)n_rp);
+    ARA_HIP(ctx, hipMemcpyAsync(h.data(), d_out, sizeof(double) * 2 * n_rp, hipMemcpyDeviceToHost, s));
+    ARA_HIP(ctx, hipStreamSynchronize(s));
+    for (int r = 0; r < n_rp; ++r) {
+        pml_out[r] = h[r];
+        tvar_out[r] = h[(size_t)n_rp + r];
+    }
+    return ARA_OK;
+}
+
+ara_status ara_debug_philox(ara_context *ctx, int64_t n, const uint32_t *d_ctr, uint64_t key,
+                            uint32_t *d_out, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!d_ctr || !d_out)))
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_debug_philox: bad arguments");
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    ARA_HIP(ctx, launch_debug_philox(n, d_ctr, key, d_out, (hipStream_t)stream));
+    return ARA_OK;
+}
+
+ara_status ara_debug_beta_quantile(ara_context *ctx, int64_t n, const float *d_a, const float *d_b,
+                                   const double *d_z, const double *d_zc, float tail_band,
+                                   float *d_x, int32_t *d_path, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!d_a || !d_b || !d_z || !d_zc || !d_x)))
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_debug_beta_quantile: bad arguments");
+    if (!(tail_band > 0.0f)) tail_band = kDefaultTailBand;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    ARA_HIP(ctx, launch_debug_quantile(n, d_a, d_b, d_z, d_zc, tail_band, d_x, d_path,
+                                       (hipStream_t)stream));
+    return ARA_OK;
+}
+
+}  // extern "C"

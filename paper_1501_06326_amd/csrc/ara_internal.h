@@ -1,0 +1,107 @@
+// ara_internal.h -- device data layout shared by the host runtime and the
+// kernels of the ARA library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ara.h"
+
+namespace ara {
+
+// Row metadata word: bits 0-15 ELT index in the layer, bits 16-19 flags,
+// bits 20-25 / 26-31 the continued-fraction terms of the (a, b) / (b, a)
+// branches of the FP32 quantile.
+enum : uint32_t {
+    ROW_DET = 1u << 16,    // loss = mean (sigma = 0 or secondary uncertainty off)
+    ROW_F64 = 1u << 17,    // shape outside the FP32 quantile's domain: FP64 path
+    ROW_CORR = 1u << 18,   // sigma_I > 0 and sigma_C > 0: mix two normals (section 3.2)
+    ROW_CONLY = 1u << 19,  // sigma_I = 0, sigma_C > 0: z = u_C
+    ROW_FLAGS = 0xFu << 16,
+};
+__host__ __device__ inline int meta_na(uint32_t m) { return (int)((m >> 20) & 63u); }
+__host__ __device__ inline int meta_nb(uint32_t m) { return (int)((m >> 26) & 63u); }
+
+// Per-layer record in device memory.
+struct LayerDev {
+    float occ_r, occ_l, agg_r, agg_l;   // layer terms (FP32; limits may be +inf)
+    int32_t elt_begin;                   // first ELT (index into EltDev[])
+    int32_t n_elts;
+    int64_t row_base;                    // first row of the layer in the row arrays
+    int64_t evoff_base;                  // first entry of the layer's ev_off[n_cat + 1]
+    int64_t otab_base;                   // first entry of the layer's otab[n_cat] (PU), or -1
+    uint32_t flags;                      // OR of the row flags of the layer
+    int32_t n_rows;
+    int32_t pad[2];
+};
+
+// Per-ELT record: id (keys the draws) and ELT financial terms.
+struct EltDev {
+    uint32_t elt_id;
+    float retention, limit, share;
+};
+
+// Per-row secondary-uncertainty constants, event-major inside each layer:
+// {max_l, alpha, beta, ln B(alpha, beta)} with ln B evaluated in FP64 at the
+// FP32 alpha, beta (so the FP32 and FP64 quantiles solve the same equation).
+struct RowQ {
+    float scale, a, b, lnb;
+};
+
+// Raw host rows staged on the device for the build kernels.
+struct RawRow {
+    int32_t event;
+    float mean, sigma_i, sigma_c, max_loss;
+};
+
+// Context-owned device status words.
+struct Status {
+    int32_t code;          // 0 or an ara_status of the first failure
+    int32_t pad;
+    int64_t where[3];      // first failing (trial, occurrence, elt_id) or row index
+};
+
+constexpr int kWave = 64;
+
+// Shapes the FP32 quantile covers (its error stays below ~1e-6 of the root
+// there); others take the FP64 path.
+constexpr float kF32MinShape = 1.0f;
+constexpr float kF32MaxShape = 32.0f;
+
+}  // namespace ara
+
+// Host-side handle definitions (not visible to the C-ABI).
+struct ara_yet {
+    ara_context *ctx;
+    int64_t n_trials;
+    int32_t n_catalogue;
+    const int64_t *d_off;
+    const int32_t *d_ev;
+    const float *d_times;
+    int64_t n_occ;
+    int64_t max_trial_len;
+};
+
+struct ara_portfolio {
+    ara_context *ctx;
+    int32_t n_catalogue;
+    int32_t n_layers;
+    int32_t n_elts;
+    int64_t n_rows;
+    uint64_t seed;
+    int32_t su_enabled;
+    int32_t max_layer_elts;
+    uint32_t all_flags;
+    ara::LayerDev *d_layers;
+    ara::EltDev *d_elts;
+    uint32_t *d_evoff;
+    ara::RowQ *d_rowq;
+    float *d_row_mean;
+    float *d_row_cfrac;
+    uint32_t *d_row_meta;
+    double *d_row_lnb;
+    float *d_otab;
+    void *d_workspace;
+    size_t workspace_bytes;
+    ara::LayerDev *h_layers;   // host copy
+};

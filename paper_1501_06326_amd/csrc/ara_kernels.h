@@ -1,0 +1,74 @@
+// ara_kernels.h -- host-side launch interface of the ARA kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ara_internal.h"
+
+namespace ara {
+
+struct PuLaunch {
+    const int64_t *off;
+    const int32_t *ev;
+    int64_t trial_begin, trial_count;
+    const float *otab;          // the layer's per-event occurrence losses [n_cat]
+    int32_t n_cat;
+    float agg_r, agg_l;
+    int32_t layer;
+    void *ylt_layers;
+    void *ylt_pf;
+    int32_t accumulate_pf;      // 0: ylt_pf = Y, 1: ylt_pf += Y
+    int grid;
+};
+
+struct SuLaunch {
+    const int64_t *off;
+    const int32_t *ev;
+    int64_t trial_begin, trial_count;
+    const LayerDev *layers;
+    int32_t n_layers;
+    const EltDev *elts;
+    const uint32_t *evoff;
+    const RowQ *rowq;
+    const float *row_mean;
+    const float *row_cfrac;
+    const uint32_t *row_meta;
+    const double *row_lnb;
+    uint64_t seed;
+    float tail_band;
+    void *ylt_layers;
+    void *ylt_pf;
+    int64_t *hits;
+    uint64_t *hit_chk;
+    Status *status;
+    int32_t *redo;            // [trial_count] scratch: trials handed to the FP64-capable pass
+    uint32_t *redo_count;     // scratch counter
+    int redo_grid;            // blocks of the second pass
+};
+
+hipError_t launch_validate_yet(const int64_t *off, const int32_t *ev, const float *times,
+                               int64_t n_trials, int32_t n_cat, Status *st,
+                               unsigned long long *max_len, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_check_rows(const RawRow *raw, int64_t n, int32_t n_cat, int32_t su, Status *st,
+                             hipStream_t s);
+hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, const EltDev *elts,
+                              LayerDev *d_layer, const LayerDev &h_layer, int32_t n_cat, int32_t su,
+                              int32_t *dat, uint32_t *evoff, RowQ *rowq, float *row_mean,
+                              float *row_cfrac, uint32_t *row_meta, double *row_lnb, float *otab,
+                              Status *st, hipStream_t s);
+hipError_t launch_pu(const PuLaunch &p, int mode, bool f64out, hipStream_t s);
+hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s);
+hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out,
+                               hipStream_t s);
+hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, const double *z,
+                                 const double *zc, float tail, float *x, int32_t *path,
+                                 hipStream_t s);
+
+// PML / TVaR (ara_select.hip)
+size_t pml_scratch_bytes(int64_t n);
+hipError_t launch_pml_tvar(const void *ylt, int32_t dtype, int64_t n, const int64_t *ks, int32_t n_rp,
+                           void *scratch, double *d_out /* [2 * n_rp]: pml, tvar */, hipStream_t s);
+
+}  // namespace ara

@@ -1,0 +1,785 @@
+// ara_kernels.hip -- gfx950 kernels of Aggregate Risk Analysis.
+//
+//  * YET validation (section 2.1 (i)).
+//  * Portfolio build (sections 3.3 and 4.2): per-ELT direct-access tables over
+//    the catalogue, the per-layer event-major row lists, the per-row Beta
+//    moment fit, and (without secondary uncertainty) the per-event
+//    occurrence-loss table.
+//  * The analysis (Algorithm 1 with secondary uncertainty):
+//      - k_ara_pu: primary uncertainty only.  The loss of an occurrence is
+//        then a function of its event id alone, so the layer's per-event
+//        occurrence losses are tabulated once (lookup, ELT terms, cross-ELT
+//        sum and occurrence terms for every catalogue event) and a trial is a
+//        gather-sum over its event ids followed by the aggregate terms.
+//      - k_ara_su: secondary uncertainty.  One wavefront per trial; lanes
+//        read consecutive occurrences, look each up in the layer's event-major
+//        rows, and append the non-zero hits to an LDS queue; the queue is
+//        drained 64 hits at a time so every lane of a batch draws, inverts
+//        the Beta CDF and applies the ELT terms on real work (the paper's
+//        "convergence switching" idea applied to SIMD lanes).  Hits in the
+//        FP64 tail band go to a second queue drained by the FP64 path.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ara_internal.h"
+#include "ara_math.h"
+#include "ara_kernels.h"
+
+namespace ara {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void report(Status *st, int32_t code, int64_t a, int64_t b, int64_t c) {
+    if (atomicCAS(&st->code, 0, code) == 0) {
+        st->where[0] = a;
+        st->where[1] = b;
+        st->where[2] = c;
+    }
+}
+
+__device__ __forceinline__ float clampf_terms(float x, float r, float l) {
+    return fminf(fmaxf(x - r, 0.0f), l);
+}
+__device__ __forceinline__ double clampd_terms(double x, double r, double l) {
+    return fmin(fmax(x - r, 0.0), l);
+}
+
+// exclusive prefix sum of v over the 64 lanes of the wavefront (lane order)
+__device__ __forceinline__ int wave_excl_scan(int v, int *total) {
+    const int lane = threadIdx.x & 63;
+    int s = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int o = __shfl_up(s, d, 64);
+        if (lane >= d) s += o;
+    }
+    *total = __shfl(s, 63, 64);
+    return s - v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Sum accumulators for a trial's occurrence losses (ara_run_opts.sum_mode).
+template <int MODE>
+struct Acc;
+template <>
+struct Acc<ARA_SUM_NAIVE32> {
+    float s = 0.0f;
+    __device__ void add(float v) { s += v; }
+    __device__ double total() {
+        float t = s;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+        return (double)t;
+    }
+};
+template <>
+struct Acc<ARA_SUM_KAHAN32> {
+    float s = 0.0f, c = 0.0f;   // Neumaier: exact sum = s + c (up to c's rounding)
+    __device__ void add(float v) {
+        const float t = s + v;
+        c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
+        s = t;
+    }
+    __device__ double total() {
+        float S = s, C = c;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const float So = __shfl_xor(S, d, 64), Co = __shfl_xor(C, d, 64);
+            // both lanes of a pair compute the same combination (symmetric order)
+            const float a = fmaxf(fabsf(S), fabsf(So)) == fabsf(S) ? S : So;
+            const float b = (a == S) ? So : S;
+            const float t = a + b;
+            const float e = (a - t) + b;
+            C = C + Co + e;
+            S = t;
+        }
+        return (double)S + (double)C;
+    }
+};
+template <>
+struct Acc<ARA_SUM_F64> {
+    double s = 0.0;
+    __device__ void add(float v) { s += (double)v; }
+    __device__ double total() {
+        double t = s;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+        return t;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// YET validation: one wavefront per trial
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_validate_yet(const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ ev,
+                                                      const float *__restrict__ times,
+                                                      int64_t n_trials, int32_t n_cat,
+                                                      Status *st, unsigned long long *max_len) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+    if (wid == 0 && lane == 0 && off[0] != 0) report(st, ARA_E_OFFSETS_NOT_MONOTONE, 0, off[0], 0);
+    const int64_t n_occ = off[n_trials];
+    for (int64_t t = wid; t < n_trials; t += nw) {
+        const int64_t a = off[t], b = off[t + 1];
+        // a trial is read only when it lies inside [0, offsets[n_trials])
+        if (a < 0 || b < a || b > n_occ) {
+            if (lane == 0) report(st, ARA_E_OFFSETS_NOT_MONOTONE, t, a, b);
+            continue;
+        }
+        if (lane == 0) atomicMax(max_len, (unsigned long long)(b - a));
+        for (int64_t j = a + lane; j < b; j += 64) {
+            const int32_t e = ev[j];
+            if (e < 0 || e >= n_cat) report(st, ARA_E_EVENT_ID_RANGE, t, j - a, e);
+            if (times && j + 1 < b && !(times[j] <= times[j + 1]))
+                report(st, ARA_E_TIMES_UNSORTED, t, j - a, 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// portfolio build
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Row checks that need no other row: finite, non-negative, mean < max_loss
+// where the row has secondary uncertainty, event id in range.
+__global__ void k_check_rows(const RawRow *__restrict__ raw, int64_t n, int32_t n_cat,
+                             int32_t su, Status *st) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const RawRow r = raw[i];
+        bool bad = !(r.mean >= 0.0f && r.sigma_i >= 0.0f && r.sigma_c >= 0.0f) ||
+                   !isfinite(r.mean) || !isfinite(r.sigma_i) || !isfinite(r.sigma_c);
+        if (su && (r.sigma_i + r.sigma_c) > 0.0f)
+            bad = bad || !(r.max_loss > r.mean) || !isfinite(r.max_loss);
+        if (r.event < 0 || r.event >= n_cat) report(st, ARA_E_EVENT_ID_RANGE, -1, i, r.event);
+        else if (bad) report(st, ARA_E_BAD_ELT_ROW, -1, i, 0);
+    }
+}
+
+// Direct-access tables of one layer: dat[j * n_cat + event] = raw row index
+// for the layer's ELT j (section 4.2).  A second row for the same event in
+// one ELT is a duplicate.
+__global__ void k_dat_scatter(const RawRow *__restrict__ raw, const int64_t *__restrict__ elt_row_off,
+                              int32_t elt_begin, int32_t n_elts, int32_t n_cat,
+                              int32_t *__restrict__ dat, Status *st) {
+    const int64_t r0 = elt_row_off[elt_begin], r1 = elt_row_off[elt_begin + n_elts];
+    for (int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < r1;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_elts - 1;   // ELT of row r
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (elt_row_off[elt_begin + mid] <= r) lo = mid; else hi = mid - 1;
+        }
+        const int32_t e = raw[r].event;
+        if (e < 0 || e >= n_cat) continue;
+        const int32_t old = atomicCAS(&dat[(int64_t)lo * n_cat + e], -1, (int32_t)(r - r0));
+        if (old != -1) report(st, ARA_E_BAD_ELT_ROW, -2, r, e);
+    }
+}
+
+__global__ void k_ev_count(const int32_t *__restrict__ dat, int32_t n_elts, int32_t n_cat,
+                           uint32_t *__restrict__ evoff) {
+    for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e <= n_cat; e += gridDim.x * blockDim.x) {
+        uint32_t c = 0;
+        if (e < n_cat)
+            for (int j = 0; j < n_elts; ++j) c += dat[(int64_t)j * n_cat + e] >= 0;
+        evoff[e] = c;
+    }
+}
+
+// In-place exclusive scan of n values with one 1024-thread block.
+__global__ __launch_bounds__(1024) void k_scan_excl_u32(uint32_t *p, int64_t n) {
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t a = tid * per, b = a + per < n ? a + per : n;
+    uint32_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += p[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        uint32_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - s;
+    for (int64_t i = a; i < b; ++i) {
+        const uint32_t v = p[i];
+        p[i] = run;
+        run += v;
+    }
+}
+
+// Beta moment fit of section 3.3 in FP64, then rounded shape parameters.
+__device__ void fit_row(const RawRow &r, int32_t su, RowQ *q, uint32_t *flags, float *cfrac,
+                        double *lnb64) {
+    const double mu = r.mean, si = r.sigma_i, sc = r.sigma_c, mx = r.max_loss;
+    const double sigma = si + sc;
+    *cfrac = 0.0f;
+    if (!su || sigma == 0.0) {
+        *flags = ROW_DET;
+        q->scale = r.mean;
+        q->a = q->b = q->lnb = 0.0f;
+        *lnb64 = 0.0;
+        return;
+    }
+    const double mu_b = mu / mx;
+    double s_b = sigma / mx;
+    const double s_max = sqrt(mu_b * (1.0 - mu_b));
+    bool capped = false;
+    if (s_b >= s_max) {
+        s_b = (1.0 - 1e-6) * s_max;
+        capped = true;
+    }
+    const double rr = s_max / s_b;
+    const double kappa = rr * rr - 1.0;
+    const float a = (float)(mu_b * kappa), b = (float)((1.0 - mu_b) * kappa);
+    const double lnb = lgamma((double)a) + lgamma((double)b) - lgamma((double)a + (double)b);
+    q->scale = r.max_loss;
+    q->a = a;
+    q->b = b;
+    q->lnb = (float)(lnb * 1.4426950408889634);   // log2 B(a, b)
+    *lnb64 = lnb;
+    uint32_t f = 0;
+    if (capped || !(a >= kF32MinShape && b >= kF32MinShape && a <= kF32MaxShape &&
+                    b <= kF32MaxShape)) {
+        f |= ROW_F64;
+    } else {
+        const int na = cf_terms((double)a, (double)b), nb = cf_terms((double)b, (double)a);
+        if (na == 0 || nb == 0) f |= ROW_F64;
+        else f |= ((uint32_t)na << 20) | ((uint32_t)nb << 26);
+    }
+    if (si > 0.0 && sc > 0.0) {
+        f |= ROW_CORR;
+        *cfrac = (float)(sc / sigma);
+    } else if (si == 0.0) {
+        f |= ROW_CONLY;
+    }
+    *flags = f;
+}
+
+// Event-major rows of one layer: for every catalogue event, its rows in the
+// layer's ELT order, with the fitted Beta constants; also the per-event
+// occurrence loss table when secondary uncertainty is off.
+__global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restrict__ raw,
+                          const int64_t *__restrict__ elt_row_off, const EltDev *__restrict__ elts,
+                          LayerDev *__restrict__ layer, int32_t n_cat, int32_t su,
+                          const uint32_t *__restrict__ evoff, RowQ *__restrict__ rowq,
+                          float *__restrict__ row_mean, float *__restrict__ row_cfrac,
+                          uint32_t *__restrict__ row_meta, double *__restrict__ row_lnb,
+                          float *__restrict__ otab) {
+    const LayerDev L = *layer;
+    uint32_t fl_or = 0;
+    for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_cat; e += gridDim.x * blockDim.x) {
+        int64_t pos = L.row_base + evoff[e];
+        float X = 0.0f;
+        for (int j = 0; j < L.n_elts; ++j) {
+            const int32_t r = dat[(int64_t)j * n_cat + e];
+            if (r < 0) continue;
+            const RawRow rr = raw[elt_row_off[L.elt_begin] + r];
+            RowQ q;
+            uint32_t f;
+            float cf;
+            double lb;
+            fit_row(rr, su, &q, &f, &cf, &lb);
+            row_lnb[pos] = lb;
+            rowq[pos] = q;
+            row_mean[pos] = rr.mean;
+            row_cfrac[pos] = cf;
+            row_meta[pos] = f | (uint32_t)j;
+            fl_or |= f & ROW_FLAGS;
+            ++pos;
+            const EltDev ed = elts[L.elt_begin + j];
+            X += ed.share * clampf_terms(rr.mean, ed.retention, ed.limit);
+        }
+        if (otab) otab[L.otab_base + e] = clampf_terms(X, L.occ_r, L.occ_l);
+    }
+    if (fl_or) atomicOr(&layer->flags, fl_or);
+}
+
+// ---------------------------------------------------------------------------
+// primary uncertainty: per-event occurrence-loss table, gather-sum per trial
+// ---------------------------------------------------------------------------
+template <int MODE, bool F64OUT, bool LDS_TAB>
+__global__ __launch_bounds__(256) void k_ara_pu(const int64_t *__restrict__ off,
+                                                const int32_t *__restrict__ ev,
+                                                int64_t trial_begin, int64_t trial_count,
+                                                const float *__restrict__ otab, int32_t n_cat,
+                                                float agg_r, float agg_l, int32_t layer,
+                                                void *__restrict__ ylt_layers,
+                                                void *__restrict__ ylt_pf, int32_t accumulate_pf) {
+    extern __shared__ float tab[];
+    const float *T = otab;
+    if (LDS_TAB) {
+        for (int i = threadIdx.x; i < n_cat; i += blockDim.x) tab[i] = otab[i];
+        __syncthreads();
+        T = tab;
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t t = wid; t < trial_count; t += nw) {
+        const int64_t a = off[trial_begin + t], b = off[trial_begin + t + 1];
+        Acc<MODE> acc;
+        for (int64_t j = a + lane; j < b; j += 64) acc.add(T[ev[j]]);
+        const double S = acc.total();
+        if (lane == 0) {
+            double Y;
+            if (MODE == ARA_SUM_NAIVE32 || MODE == ARA_SUM_KAHAN32) {
+                Y = (double)clampf_terms((float)S, agg_r, agg_l);
+            } else {
+                Y = clampd_terms(S, (double)agg_r, (double)agg_l);
+            }
+            if (F64OUT) {
+                if (ylt_layers) ((double *)ylt_layers)[(int64_t)layer * trial_count + t] = Y;
+                if (ylt_pf) {
+                    double *p = (double *)ylt_pf + t;
+                    *p = accumulate_pf ? *p + Y : Y;
+                }
+            } else {
+                if (ylt_layers) ((float *)ylt_layers)[(int64_t)layer * trial_count + t] = (float)Y;
+                if (ylt_pf) {
+                    float *p = (float *)ylt_pf + t;
+                    *p = accumulate_pf ? *p + (float)Y : (float)Y;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// secondary uncertainty
+// ---------------------------------------------------------------------------
+constexpr int kSeg = 1024;        // occurrences per LDS segment
+constexpr int kQCap = 512;        // hit queue (power of two)
+constexpr int kQMask = kQCap - 1;
+constexpr int kPerLane = (kQCap - kWave) / kWave;   // hits a lane appends per sub-step
+
+struct SuArgs {
+    const int64_t *off;
+    const int32_t *ev;
+    int64_t trial_begin, trial_count;
+    const LayerDev *layers;
+    int32_t n_layers;
+    const EltDev *elts;
+    const uint32_t *evoff;
+    const RowQ *rowq;
+    const float *row_mean;
+    const float *row_cfrac;
+    const uint32_t *row_meta;
+    const double *row_lnb;
+    float tail_band;
+    void *ylt_layers;
+    void *ylt_pf;
+    int64_t *hits;
+    uint64_t *hit_chk;
+    Status *status;
+    int32_t *redo;            // trials (relative index) handed to the FP64-capable pass
+    uint32_t *redo_count;
+};
+
+// The draws of a hit as 24-bit grid integers: jI keyed (k, i, elt_id, 0),
+// jC keyed (k, i, 0, 1); only those the row's flags need are drawn.
+__device__ __forceinline__ void draw_j(uint32_t flags, uint32_t k, uint32_t i, uint32_t elt_id,
+                                       const PhiloxKeys &keys, uint32_t *jI, uint32_t *jC) {
+    *jI = (flags & ROW_CONLY) ? 0u : u24(philox10_x0(make_uint4(k, i, elt_id, 0u), keys));
+    *jC = (flags & (ROW_CONLY | ROW_CORR)) ? u24(philox10_x0(make_uint4(k, i, 0u, 1u), keys)) : 0u;
+}
+
+// z and 1 - z of a hit (section 3.2).  A pure independent or correlated draw
+// is an exact grid value u = j 2^-24 (and 1 - u is exact too); the mixed case
+// maps both uniforms through Phi^-1 (= -sqrt(2) erfcinv(2u), taken on the side
+// of the smaller tail so the argument is exact), mixes, and maps back with
+// Phi(v) and Phi(-v).
+template <typename T>
+__device__ __forceinline__ void hit_z(uint32_t meta, uint32_t jI, uint32_t jC, T cfrac, T *z, T *zc) {
+    const T s24 = (T)5.9604644775390625e-08;
+    if (!(meta & ROW_CORR)) {
+        const uint32_t j = (meta & ROW_CONLY) ? jC : jI;
+        *z = (T)j * s24;
+        *zc = (T)(16777216u - j) * s24;
+        return;
+    }
+    auto nq = [&](uint32_t j) {
+        const T lo = (T)(j < 8388608u ? j : 16777216u - j) * ((T)2 * s24);
+        const T v = (T)1.4142135623730951 * erfcinv(lo);
+        return j < 8388608u ? -v : v;
+    };
+    const T wc = cfrac, wi = (T)1 - cfrac;
+    const T v = (nq(jI) * wi + nq(jC) * wc) / sqrt(wi * wi + wc * wc);
+    *z = (T)0.5 * erfc(-v * (T)0.7071067811865476);
+    *zc = (T)0.5 * erfc(v * (T)0.7071067811865476);
+}
+
+// One trial of the analysis, all layers (Algorithm 1 from the layer loop
+// down).  REDO = false is the lean FP32 pass: a hit that needs the FP64
+// quantile (tail band, shape outside the FP32 domain, FP32 non-convergence)
+// abandons the trial, which is then queued for the REDO = true pass, where
+// such hits take the FP64 path in place.  Returns true when abandoned.
+template <int MODE, bool F64OUT, bool DIAG, bool REDO>
+__device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys, int64_t t,
+                                         float *X, uint2 *Q) {
+    const int lane = threadIdx.x;
+    const int64_t ti = A.trial_begin + t;
+    const uint32_t i_abs = (uint32_t)ti;
+    const int64_t o0 = A.off[ti];
+    const int64_t n = A.off[ti + 1] - o0;
+    double pf_sum = 0.0;
+
+    for (int l = 0; l < A.n_layers; ++l) {
+        const LayerDev L = A.layers[l];
+        const uint32_t *eo = A.evoff + L.evoff_base;
+        const int64_t rb0 = L.row_base;
+        Acc<MODE> acc;
+        uint64_t chk = 0;
+        int64_t nh = 0;
+
+        for (int64_t seg = 0; seg < n; seg += kSeg) {
+            const int segn = (int)((n - seg) < kSeg ? (n - seg) : kSeg);
+            for (int i = lane; i < segn; i += kWave) X[i] = 0.0f;
+            uint32_t qh = 0, qt = 0;   // queue head / tail (wave-uniform)
+            bool abandon = false;
+            __syncthreads();
+
+            // Drain cnt queue entries from head h, one hit per lane: draw,
+            // invert the Beta CDF, ELT terms, accumulate into X[k].
+            auto run_batch = [&](uint32_t h, int cnt) {
+                __syncthreads();
+                bool defer = false;
+                if (lane < cnt) {
+                    const uint2 e = Q[(h + lane) & kQMask];
+                    const uint32_t kl = e.x, row = e.y;
+                    const uint32_t meta = A.row_meta[row];
+                    const EltDev ed = A.elts[L.elt_begin + (meta & 0xffffu)];
+                    float loss = 0.0f;
+                    if (meta & ROW_DET) {
+                        loss = A.rowq[row].scale;
+                    } else if (!REDO && (meta & (ROW_F64 | ROW_CORR))) {
+                        // shapes outside the FP32 domain and the two-normal mix
+                        // (whose special functions would inflate this pass's
+                        // register budget) are left to the second pass
+                        defer = true;
+                    } else {
+                        uint32_t jI, jC;
+                        draw_j(meta, (uint32_t)(seg + kl), i_abs, ed.elt_id, keys, &jI, &jC);
+                        float z, zc;
+                        if (REDO) {
+                            hit_z<float>(meta, jI, jC, A.row_cfrac[row], &z, &zc);
+                        } else {
+                            const uint32_t j = (meta & ROW_CONLY) ? jC : jI;
+                            z = (float)j * 5.9604644775390625e-08f;
+                            zc = (float)(16777216u - j) * 5.9604644775390625e-08f;
+                        }
+                        const RowQ q = A.rowq[row];
+                        bool need64 = (meta & ROW_F64) || fminf(z, zc) < A.tail_band;
+                        if (!need64) {
+                            bool ok;
+                            const float x = beta_quantile32(q.a, q.b, q.lnb, meta_na(meta),
+                                                            meta_nb(meta), z, zc, &ok);
+                            if (ok) loss = q.scale * x; else need64 = true;
+                        }
+                        if (need64) {
+                            if (REDO) {
+                                double z64, zc64;
+                                hit_z<double>(meta, jI, jC, (double)A.row_cfrac[row], &z64, &zc64);
+                                bool ok;
+                                const double x = beta_quantile64((double)q.a, (double)q.b,
+                                                                 A.row_lnb[row], z64, zc64, &ok);
+                                if (!ok) report(A.status, ARA_E_NUMERIC, ti, seg + kl, ed.elt_id);
+                                loss = (float)((double)q.scale * x);
+                            } else {
+                                defer = true;
+                            }
+                        }
+                    }
+                    if (DIAG) {
+                        nh += 1;
+                        chk += (uint64_t)(seg + kl + 1) * 2654435761ull + (uint64_t)ed.elt_id;
+                    }
+                    if (!defer) {
+                        const float lp = ed.share * clampf_terms(loss, ed.retention, ed.limit);
+                        atomicAdd(&X[kl], lp);
+                    }
+                }
+                if (!REDO && __any(defer)) abandon = true;
+                __syncthreads();
+            };
+
+            for (int c = 0; c < segn && !abandon; c += kWave) {
+                const int kl = c + lane;
+                const bool valid = kl < segn;
+                uint32_t rb = 0, cnt = 0;
+                if (valid) {
+                    const int32_t E = A.ev[o0 + seg + kl];
+                    rb = eo[E];
+                    cnt = eo[E + 1] - rb;
+                }
+                uint32_t done = 0;
+                while (!abandon) {
+                    const int take = (int)min(cnt - done, (uint32_t)kPerLane);
+                    int tot;
+                    const int excl = wave_excl_scan(take, &tot);
+                    if (tot == 0) break;
+                    for (int j = 0; j < take; ++j)
+                        Q[(qt + excl + j) & kQMask] =
+                            make_uint2((uint32_t)kl, (uint32_t)(rb0 + rb + done + j));
+                    qt += tot;
+                    done += take;
+                    while (qt - qh >= (uint32_t)kWave && !abandon) {
+                        run_batch(qh, kWave);
+                        qh += kWave;
+                    }
+                }
+            }
+            if (!abandon && qt != qh) run_batch(qh, (int)(qt - qh));
+            if (abandon) return true;
+            __syncthreads();
+            for (int i = lane; i < segn; i += kWave)
+                acc.add(clampf_terms(X[i], L.occ_r, L.occ_l));
+            __syncthreads();
+        }
+
+        const double S = acc.total();
+        double Y;
+        if (MODE == ARA_SUM_F64) Y = clampd_terms(S, (double)L.agg_r, (double)L.agg_l);
+        else Y = (double)clampf_terms((float)S, L.agg_r, L.agg_l);
+        if (DIAG) {
+            nh = wave_sum(nh);
+            chk = wave_sum(chk);
+        }
+        if (lane == 0) {
+            if (F64OUT) {
+                if (A.ylt_layers) ((double *)A.ylt_layers)[(int64_t)l * A.trial_count + t] = Y;
+            } else {
+                if (A.ylt_layers) ((float *)A.ylt_layers)[(int64_t)l * A.trial_count + t] = (float)Y;
+            }
+            if (DIAG) {
+                if (A.hits) A.hits[(int64_t)l * A.trial_count + t] = nh;
+                if (A.hit_chk) A.hit_chk[(int64_t)l * A.trial_count + t] = chk;
+            }
+        }
+        if (F64OUT) pf_sum += Y;
+        else pf_sum = (double)((float)pf_sum + (float)Y);
+    }
+    if (lane == 0 && A.ylt_pf) {
+        if (F64OUT) ((double *)A.ylt_pf)[t] = pf_sum;
+        else ((float *)A.ylt_pf)[t] = (float)pf_sum;
+    }
+    return false;
+}
+
+// Main pass: one wavefront (block) per trial.
+template <int MODE, bool F64OUT, bool DIAG>
+__global__ __launch_bounds__(64) void k_ara_su(SuArgs A, PhiloxKeys keys) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    const int64_t t = blockIdx.x;
+    if (t >= A.trial_count) return;
+    if (su_trial<MODE, F64OUT, DIAG, false>(A, keys, t, X, Q) && threadIdx.x == 0)
+        A.redo[atomicAdd(A.redo_count, 1u)] = (int32_t)t;
+}
+
+// FP64-capable pass over the trials the main pass handed over; the count is
+// read on the device, so no host round trip is needed between the passes.
+template <int MODE, bool F64OUT, bool DIAG>
+__global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    const uint32_t n = *A.redo_count;
+    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x)
+        su_trial<MODE, F64OUT, DIAG, true>(A, keys, (int64_t)A.redo[r], X, Q);
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics
+// ---------------------------------------------------------------------------
+__global__ void k_debug_philox(int64_t n, const uint32_t *__restrict__ ctr, PhiloxKeys keys,
+                               uint32_t *__restrict__ out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 c = make_uint4(ctr[4 * j], ctr[4 * j + 1], ctr[4 * j + 2], ctr[4 * j + 3]);
+        const uint4 r = philox10(c, keys);
+        out[4 * j] = r.x;
+        out[4 * j + 1] = r.y;
+        out[4 * j + 2] = r.z;
+        out[4 * j + 3] = r.w;
+        if (philox10_x0(c, keys) != r.x) out[4 * j] = ~r.x;   // both forms must agree
+    }
+}
+
+__global__ __launch_bounds__(64) void k_debug_quantile(int64_t n, const float *__restrict__ a,
+                                                       const float *__restrict__ b,
+                                                       const double *__restrict__ z,
+                                                       const double *__restrict__ zc, float tail,
+                                                       float *__restrict__ x,
+                                                       int32_t *__restrict__ path) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float A = a[j], B = b[j];
+    const float zf = (float)z[j], zcf = (float)zc[j];
+    const bool shape_ok = A >= kF32MinShape && B >= kF32MinShape && A <= kF32MaxShape &&
+                          B <= kF32MaxShape;
+    bool use64 = !shape_ok || fminf(zf, zcf) < tail;
+    const double lnb = lgamma((double)A) + lgamma((double)B) - lgamma((double)A + (double)B);
+    float r = 0.0f;
+    if (!use64) {
+        const int na = cf_terms((double)A, (double)B), nb = cf_terms((double)B, (double)A);
+        if (na == 0 || nb == 0) use64 = true;
+        else {
+            bool ok;
+            r = beta_quantile32(A, B, (float)(lnb * 1.4426950408889634), na, nb, zf, zcf, &ok);
+            if (!ok) use64 = true;
+        }
+    }
+    if (use64) {
+        bool ok;
+        r = (float)beta_quantile64((double)A, (double)B, lnb, z[j], zc[j], &ok);
+        if (!ok) r = __builtin_nanf("");
+    }
+    x[j] = r;
+    if (path) path[j] = use64 ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int64_t n, int block, int cap = 65536) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_validate_yet(const int64_t *off, const int32_t *ev, const float *times,
+                               int64_t n_trials, int32_t n_cat, Status *st,
+                               unsigned long long *max_len, hipStream_t s) {
+    const int g = grid_for(n_trials, 4, 262144);
+    hipLaunchKernelGGL(k_validate_yet, dim3(g), dim3(256), 0, s, off, ev, times, n_trials, n_cat,
+                       st, max_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_rows(const RawRow *raw, int64_t n, int32_t n_cat, int32_t su, Status *st,
+                             hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, raw, n, n_cat, su, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, const EltDev *elts,
+                              LayerDev *d_layer, const LayerDev &h_layer, int32_t n_cat, int32_t su,
+                              int32_t *dat, uint32_t *evoff, RowQ *rowq, float *row_mean,
+                              float *row_cfrac, uint32_t *row_meta, double *row_lnb, float *otab,
+                              Status *st, hipStream_t s) {
+    const int64_t nd = (int64_t)h_layer.n_elts * n_cat;
+    hipError_t e = launch_fill_i32(dat, nd > 0 ? nd : 1, -1, s);
+    if (e != hipSuccess) return e;
+    if (h_layer.n_rows > 0)
+        hipLaunchKernelGGL(k_dat_scatter, dim3(grid_for(h_layer.n_rows, 256)), dim3(256), 0, s,
+                           raw, elt_row_off, h_layer.elt_begin, h_layer.n_elts, n_cat, dat, st);
+    uint32_t *eo = evoff + h_layer.evoff_base;
+    hipLaunchKernelGGL(k_ev_count, dim3(grid_for((int64_t)n_cat + 1, 256)), dim3(256), 0, s, dat,
+                       h_layer.n_elts, n_cat, eo);
+    hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, eo, (int64_t)n_cat + 1);
+    hipLaunchKernelGGL(k_ev_fill, dim3(grid_for(n_cat, 256)), dim3(256), 0, s, dat, raw,
+                       elt_row_off, elts, d_layer, n_cat, su, eo, rowq, row_mean, row_cfrac,
+                       row_meta, row_lnb, otab);
+    return hipGetLastError();
+}
+
+template <int MODE, bool F64OUT>
+static hipError_t pu_dispatch(const PuLaunch &p, hipStream_t s) {
+    const int block = 256;
+    const size_t lds = (size_t)p.n_cat * sizeof(float);
+    const bool use_lds = lds <= 64 * 1024;
+    int g = p.grid;
+    if (use_lds)
+        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, true>), dim3(g), dim3(block), lds, s, p.off,
+                           p.ev, p.trial_begin, p.trial_count, p.otab, p.n_cat, p.agg_r, p.agg_l,
+                           p.layer, p.ylt_layers, p.ylt_pf, p.accumulate_pf);
+    else
+        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, false>), dim3(g), dim3(block), 0, s, p.off,
+                           p.ev, p.trial_begin, p.trial_count, p.otab, p.n_cat, p.agg_r, p.agg_l,
+                           p.layer, p.ylt_layers, p.ylt_pf, p.accumulate_pf);
+    return hipGetLastError();
+}
+
+hipError_t launch_pu(const PuLaunch &p, int mode, bool f64out, hipStream_t s) {
+    if (mode == ARA_SUM_NAIVE32) return f64out ? pu_dispatch<ARA_SUM_NAIVE32, true>(p, s)
+                                               : pu_dispatch<ARA_SUM_NAIVE32, false>(p, s);
+    if (mode == ARA_SUM_KAHAN32) return f64out ? pu_dispatch<ARA_SUM_KAHAN32, true>(p, s)
+                                               : pu_dispatch<ARA_SUM_KAHAN32, false>(p, s);
+    return f64out ? pu_dispatch<ARA_SUM_F64, true>(p, s) : pu_dispatch<ARA_SUM_F64, false>(p, s);
+}
+
+template <int MODE, bool F64OUT>
+static hipError_t su_dispatch2(const SuLaunch &p, hipStream_t s) {
+    SuArgs A;
+    A.off = p.off; A.ev = p.ev; A.trial_begin = p.trial_begin; A.trial_count = p.trial_count;
+    A.layers = p.layers; A.n_layers = p.n_layers; A.elts = p.elts; A.evoff = p.evoff;
+    A.rowq = p.rowq; A.row_mean = p.row_mean; A.row_cfrac = p.row_cfrac; A.row_meta = p.row_meta;
+    A.row_lnb = p.row_lnb;
+    A.tail_band = p.tail_band; A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf;
+    A.hits = p.hits; A.hit_chk = p.hit_chk; A.status = p.status;
+    A.redo = p.redo; A.redo_count = p.redo_count;
+    const PhiloxKeys keys = philox_keys(p.seed);
+    hipError_t e = hipMemsetAsync(p.redo_count, 0, sizeof(uint32_t), s);
+    if (e != hipSuccess) return e;
+    const dim3 g((unsigned)p.trial_count), gr((unsigned)p.redo_grid);
+    if (p.hits || p.hit_chk) {
+        hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, true>), g, dim3(64), 0, s, A, keys);
+        hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, true>), gr, dim3(64), 0, s, A, keys);
+    } else {
+        hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, false>), g, dim3(64), 0, s, A, keys);
+        hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, false>), gr, dim3(64), 0, s, A, keys);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s) {
+    if (p.trial_count <= 0) return hipSuccess;
+    if (mode == ARA_SUM_NAIVE32) return f64out ? su_dispatch2<ARA_SUM_NAIVE32, true>(p, s)
+                                               : su_dispatch2<ARA_SUM_NAIVE32, false>(p, s);
+    if (mode == ARA_SUM_KAHAN32) return f64out ? su_dispatch2<ARA_SUM_KAHAN32, true>(p, s)
+                                               : su_dispatch2<ARA_SUM_KAHAN32, false>(p, s);
+    return f64out ? su_dispatch2<ARA_SUM_F64, true>(p, s) : su_dispatch2<ARA_SUM_F64, false>(p, s);
+}
+
+hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_philox, dim3(grid_for(n, 256)), dim3(256), 0, s, n, ctr,
+                       philox_keys(key), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, const double *z,
+                                 const double *zc, float tail, float *x, int32_t *path,
+                                 hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_quantile, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, a, b,
+                       z, zc, tail, x, path);
+    return hipGetLastError();
+}
+
+}  // namespace ara

@@ -1,0 +1,241 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
+
+Tolerances (written here, derived in the design notes):
+  * lookups, Philox words, hit counts and hit checksums: bit-exact;
+  * per-trial loss:  |Y_gpu - Y_oracle| <= 1e-5 * G_oracle (+1e-3 absolute),
+    G = the trial's gross loss sum_k X_k (FP32 error enters at that scale
+    because every clamp of the method is 1-Lipschitz);
+  * PML / TVaR end to end: 1e-6 relative;
+  * PML on the same YLT: bit-identical to numpy's k-th largest; TVaR 1e-12.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.tiny import A, B, random_tiny_case, worked_example
+from workloads import config_small, make_yet
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+T2 = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ara():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1501_06326_amd import Ara
+    a = Ara(0)
+    yield a
+    a.close()
+
+
+def check_t2(got, ref, what):
+    g = got.double().cpu().numpy() if hasattr(got, "cpu") else got
+    err = np.abs(g - ref["ylt"])
+    tol = T2 * ref["gross"] + 1e-3
+    bad = np.argwhere(err > tol)
+    assert bad.size == 0, (what, bad[:5], g[tuple(bad[0])], ref["ylt"][tuple(bad[0])])
+    return float((err / np.maximum(ref["gross"], 1.0)).max())
+
+
+# --------------------------------------------------------------------------
+def test_philox_bit_exact(ara):
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(1 << 20, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4096] = 0
+    ctr[:4096, 0] = np.arange(4096)
+    for key in (0, 150106326, 0xFFFFFFFFFFFFFFFF, 0x9ABCDEF012345678):
+        say("philox key", key)
+        got = ara.debug_philox(ctr, key)
+        ref = oracle.philox4x32_10(ctr, np.array([key & 0xFFFFFFFF, key >> 32], np.uint32))
+        assert np.array_equal(got, ref)
+
+
+QUANTILE_SHAPES = [(2.75, 8.25), (1.0, 1.0), (1.0, 3.0), (3.0, 1.0), (1.2, 3.0), (30.0, 70.0),
+                   (200.0, 300.0), (1.01, 50.0), (50.0, 1.01), (0.5, 0.5), (0.7, 5.0),
+                   (5.0, 0.7), (0.01, 0.02), (2000.0, 3000.0)]
+
+
+@pytest.mark.parametrize("a,b", QUANTILE_SHAPES)
+def test_beta_quantile_accuracy(ara, a, b):
+    """Per-draw accuracy against the FP64 oracle on the 2^-24 draw grid.
+    Bound: the paper's convergence criterion (relative error < 1e-6,
+    section 5.1) on |x - x_ref| / max(x_ref, mean), i.e. relative to the
+    root where it is not tiny and to the distribution's mean below that."""
+    rng = np.random.default_rng(7)
+    j = np.concatenate([np.array([1, 3, 2 ** 23 - 1, 2 ** 23 + 1, 2 ** 24 - 3, 2 ** 24 - 1]),
+                        (rng.integers(0, 2 ** 23, size=20000) * 2 + 1)]).astype(np.float64)
+    z = j / 2 ** 24
+    zc = (2 ** 24 - j) / 2 ** 24
+    af = np.float32(a)
+    bf = np.float32(b)
+    say("quantile shape", a, b)
+    x, path = ara.debug_beta_quantile(np.full(z.size, af), np.full(z.size, bf), z, zc)
+    ref = oracle.betaincinv(float(af), float(bf), z, zc)
+    assert np.all(np.isfinite(x))
+    scale = np.maximum(ref, float(af) / (float(af) + float(bf)))
+    err = np.abs(x.astype(np.float64) - ref) / scale
+    say(f"  path64 share {path.mean():.4f}  max {err.max():.3g}  p99 {np.percentile(err, 99):.3g}")
+    assert err.max() < 1e-6
+    in_f32 = 1.0 <= af <= 32.0 and 1.0 <= bf <= 32.0
+    if in_f32:
+        # only the 2^-20 tail band (and nothing else) may leave the FP32 path
+        assert path.mean() < 1e-3
+
+
+def test_worked_example_exact(ara):
+    yet, pf = worked_example(trials=[[A, B, A], [B], [], [A, A, A]])
+    say("worked example PU")
+    y = ara.load_yet(yet)
+    p = ara.load_portfolio(pf, yet.n_catalogue)
+    r = ara.run(y, p)
+    assert r["ylt"].cpu().numpy()[0].tolist() == [6.0e5, 0.0, 0.0, 3.4e6]
+    pf.su_enabled = True     # sigma = 0 rows: the secondary-uncertainty kernel must agree
+    p2 = ara.load_portfolio(pf, yet.n_catalogue)
+    r2 = ara.run(y, p2, diagnostics=True)
+    assert r2["ylt"].cpu().numpy()[0].tolist() == [6.0e5, 0.0, 0.0, 3.4e6]
+    assert r2["hits"].cpu().numpy()[0].tolist() == [5, 1, 0, 6]
+
+
+@pytest.mark.parametrize("su", [False, True])
+def test_small_config_parity(ara, su):
+    w = config_small(su=su)
+    say("small config su", su, w.yet.n_trials, w.yet.n_occ)
+    ref = oracle.run_ara(w.yet, w.portfolio)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    r = ara.run(y, p, diagnostics=su)
+    m = check_t2(r["ylt"], ref, "small")
+    say(f"  max |dY|/G = {m:.3g}")
+    pf_ref = ref["ylt_pf"]
+    pf_got = r["ylt_pf"].double().cpu().numpy()
+    assert np.all(np.abs(pf_got - pf_ref) <= T2 * ref["gross"].sum(0) + 1e-3)
+    if su:
+        assert np.array_equal(r["hits"].cpu().numpy(), ref["hits"])
+        assert np.array_equal(r["hit_chk"].cpu().numpy().view(np.uint64), ref["hit_chk"])
+    pml, tvar = ara.pml_tvar(r["ylt_pf"], w.return_periods)
+    opml, otvar = oracle.pml_tvar(pf_ref, w.return_periods)
+    say(f"  PML {pml} vs {opml}; TVaR {tvar} vs {otvar}")
+    np.testing.assert_allclose(pml, opml, rtol=1e-6)
+    np.testing.assert_allclose(tvar, otvar, rtol=1e-6)
+
+
+def test_small_config_correlated(ara):
+    w = config_small(corr=True, n_trials=3000)
+    say("small correlated", w.yet.n_trials)
+    ref = oracle.run_ara(w.yet, w.portfolio)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    r = ara.run(y, p, diagnostics=True)
+    check_t2(r["ylt"], ref, "corr")
+    assert np.array_equal(r["hits"].cpu().numpy(), ref["hits"])
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("su,corr", [(False, False), (True, False), (True, True)])
+def test_tiny_random_portfolios(ara, seed, su, corr):
+    rng = np.random.default_rng(1000 + seed)
+    yet, pf = random_tiny_case(rng, n_cat=40, n_layers=3, max_elts=4, max_occ=30, n_trials=64,
+                               dyadic=False, su=su, corr=corr)
+    say("tiny", seed, su, corr)
+    ref = oracle.run_ara(yet, pf)
+    y = ara.load_yet(yet)
+    p = ara.load_portfolio(pf, yet.n_catalogue)
+    r = ara.run(y, p, diagnostics=su)
+    check_t2(r["ylt"], ref, f"tiny {seed}")
+    if su:
+        assert np.array_equal(r["hits"].cpu().numpy(), ref["hits"])
+
+
+def test_determinism_and_slicing(ara):
+    w = config_small(n_trials=3000)
+    say("determinism")
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    a = ara.run(y, p)["ylt"].cpu().numpy()
+    b = ara.run(y, p)["ylt"].cpu().numpy()
+    assert np.array_equal(a, b)
+    c1 = ara.run(y, p, trial_begin=0, trial_count=1234)["ylt"].cpu().numpy()
+    c2 = ara.run(y, p, trial_begin=1234, trial_count=3000 - 1234)["ylt"].cpu().numpy()
+    assert np.array_equal(np.concatenate([c1, c2], axis=1), a)
+
+
+@pytest.mark.parametrize("mode", ["naive32", "kahan32", "f64"])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sum_modes(ara, mode, dtype):
+    w = config_small(n_trials=2000)
+    say("sum mode", mode, dtype)
+    ref = oracle.run_ara(w.yet, w.portfolio)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    r = ara.run(y, p, sum_mode=mode, ylt_dtype=dtype)
+    assert r["ylt"].dtype == (torch.float64 if dtype == "f64" else torch.float32)
+    check_t2(r["ylt"], ref, mode)
+
+
+def test_pml_tvar_on_same_ylt(ara):
+    rng = np.random.default_rng(5)
+    for n, dt in [(1_000_000, np.float32), (12345, np.float32), (777, np.float64), (50, np.float32)]:
+        v = rng.lognormal(14, 2, size=n).astype(dt)
+        v[rng.random(n) < 0.3] = 0
+        v[:10] = v[10]           # ties
+        t = torch.from_numpy(v).cuda()
+        rps = [100.0, 250.0, 1.0, 2.0, 1e9]
+        say("pml", n, dt)
+        pml, tvar = ara.pml_tvar(t, rps)
+        s = np.sort(v.astype(np.float64))[::-1]
+        for r_, rp in enumerate(rps):
+            k = max(1, int(math.floor(n / rp)))
+            assert pml[r_] == s[k - 1]
+            assert abs(tvar[r_] - math.fsum(s[:k]) / k) <= 1e-12 * abs(tvar[r_]) + 1e-300
+
+
+def test_input_errors(ara):
+    from paper_1501_06326_amd.ara import (ARA_E_BAD_ELT_ROW, ARA_E_EVENT_ID_RANGE,
+                                          ARA_E_OFFSETS_NOT_MONOTONE, ARA_E_TIMES_UNSORTED,
+                                          AraError)
+    yet, pf = worked_example()
+    say("errors")
+    bad = make_yet(5, 4.0, 4, 1)
+    bad.event_ids[3] = 7
+    with pytest.raises(AraError) as e:
+        ara.load_yet(bad)
+    assert e.value.code == ARA_E_EVENT_ID_RANGE
+    bad = make_yet(5, 4.0, 4, 1)
+    bad.times[bad.offsets[1]:bad.offsets[2]] = bad.times[bad.offsets[1]:bad.offsets[2]][::-1]
+    if bad.offsets[2] - bad.offsets[1] > 1 and bad.times[bad.offsets[1]] != bad.times[bad.offsets[1] + 1]:
+        with pytest.raises(AraError) as e:
+            ara.load_yet(bad)
+        assert e.value.code == ARA_E_TIMES_UNSORTED
+    from tests.tiny import yet_from_lists
+    bad = yet_from_lists([[0, 1, 2], [3, 0], [1, 1, 2], [0, 3]], 4)
+    bad.offsets[2] = 2                                  # offsets 0, 3, 2, 8, 10
+    with pytest.raises(AraError) as e:
+        ara.load_yet(bad)
+    assert e.value.code == ARA_E_OFFSETS_NOT_MONOTONE
+    e1 = pf.layers[0].elts[0]
+    e1.event_ids = np.array([A, A], np.int32)        # duplicate event in one ELT
+    with pytest.raises(AraError) as e:
+        ara.load_portfolio(pf, 4)
+    assert e.value.code == ARA_E_BAD_ELT_ROW
+    yet, pf = worked_example()
+    pf.su_enabled = True
+    e1 = pf.layers[0].elts[0]
+    e1.sigma_i = np.array([1.0, 1.0], np.float32)
+    e1.max_loss = e1.mean.copy()                        # mean >= max_loss with sigma > 0
+    with pytest.raises(AraError) as e:
+        ara.load_portfolio(pf, 4)
+    assert e.value.code == ARA_E_BAD_ELT_ROW
+    yet, pf = worked_example()
+    y = ara.load_yet(yet)
+    p = ara.load_portfolio(pf, 8)                       # catalogue mismatch
+    with pytest.raises(AraError):
+        ara.run(y, p)
