@@ -25,12 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# 256 CUs x 64 lanes x 2.4 GHz: one 32-bit VALU lane operation per lane per
-# cycle (no packed FP32; the library is built without packed-FP32 ops)
-PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU issue peak in 32-bit lane operations: the FP32 vector peak of
+# 157.3 TFLOP/s counts an FMA as two flops, i.e. 256 CUs x 128 lanes x 2.4 GHz
+# = 78.6e12 lane operations per second.
+PEAK_VALU_TOPS = 157.3 / 2.0
 # VALU lane operations per secondary-uncertainty draw of the main kernel at the
-# full-shape workload (SQ_INSTS_VALU x 64 / draws, measured with rocprofv3)
-VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "0") or 0)
+# full-shape workload: SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/).
+VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "659"))
 
 
 def log(*a):
@@ -47,6 +48,9 @@ def main():
     ap.add_argument("--no-pu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sum-mode", default="naive32")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (a known-size kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -77,6 +81,12 @@ def main():
     scratch = torch.empty(ara.run_scratch_size(n), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     log("loaded YET and portfolio")
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(portfolio):
         ara.run(y, portfolio, sum_mode=args.sum_mode, out_layers=out_l, out_pf=out_p,

@@ -61,8 +61,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Byte layout of a portfolio workspace.
 struct Layout {
-    size_t layers, elts, evoff, rowq, row_mean, row_cfrac, row_meta, row_lnb, otab, raw, eltoff, dat,
-        total;
+    size_t layers, elts, evoff, rowq, row_mean, row_cfrac, row_meta, row_lnb, otab, sp_bits, sp_rank,
+        sp_vals, raw, eltoff, dat, total;
     int64_t n_rows = 0;
     int32_t n_elts = 0, max_layer_elts = 0;
 };
@@ -108,7 +108,12 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
     L->row_cfrac = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
     L->row_meta = o; o += align256(sizeof(uint32_t) * (size_t)(rows ? rows : 1));
     L->row_lnb = o; o += align256(sizeof(double) * (size_t)(rows ? rows : 1));
-    L->otab = o; o += d->su_enabled ? 0 : align256(sizeof(float) * (size_t)nl * n_cat);
+    const size_t nw = ((size_t)n_cat + 31) / 32;
+    const bool pu = !d->su_enabled;
+    L->otab = o; o += pu ? align256(sizeof(float) * (size_t)nl * n_cat) : 0;
+    L->sp_bits = o; o += pu ? align256(sizeof(uint32_t) * (size_t)nl * nw) : 0;
+    L->sp_rank = o; o += pu ? align256(sizeof(uint32_t) * (size_t)nl * (nw + 1)) : 0;
+    L->sp_vals = o; o += pu ? align256(sizeof(float) * (size_t)nl * n_cat) : 0;
     L->raw = o; o += align256(sizeof(RawRow) * (size_t)(rows ? rows : 1));
     L->eltoff = o; o += align256(sizeof(int64_t) * (size_t)(ne + 1));
     L->dat = o; o += align256(sizeof(int32_t) * (size_t)(mx ? mx : 1) * n_cat);
@@ -343,6 +348,9 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
     p->d_row_meta = (uint32_t *)(w + L.row_meta);
     p->d_row_lnb = (double *)(w + L.row_lnb);
     p->d_otab = desc->su_enabled ? nullptr : (float *)(w + L.otab);
+    p->d_sp_bits = desc->su_enabled ? nullptr : (uint32_t *)(w + L.sp_bits);
+    p->d_sp_rank = desc->su_enabled ? nullptr : (uint32_t *)(w + L.sp_rank);
+    p->d_sp_vals = desc->su_enabled ? nullptr : (float *)(w + L.sp_vals);
     p->d_workspace = d_workspace;
     p->workspace_bytes = bytes;
     RawRow *d_raw = (RawRow *)(w + L.raw);
@@ -377,11 +385,17 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
         ara_status cs = check_status(ctx, s, "ara_load_portfolio");
         if (cs != ARA_OK) return cleanup(cs);
     }
+    const size_t nwc = ((size_t)n_catalogue + 31) / 32;
     for (int l = 0; l < nl; ++l) {
         ARA_HIP_P(launch_build_layer(d_raw, d_eltoff, p->d_elts, p->d_layers + l, hl[l], n_catalogue,
                                      p->su_enabled, d_dat, p->d_evoff, p->d_rowq, p->d_row_mean,
                                      p->d_row_cfrac, p->d_row_meta, p->d_row_lnb, p->d_otab,
                                      ctx->d_status, s));
+        if (!p->su_enabled)
+            ARA_HIP_P(launch_build_sparse(p->d_otab + (size_t)l * n_catalogue, n_catalogue,
+                                          p->d_sp_bits + (size_t)l * nwc,
+                                          p->d_sp_rank + (size_t)l * (nwc + 1),
+                                          p->d_sp_vals + (size_t)l * n_catalogue, p->d_layers + l, s));
     }
     p->h_layers = new LayerDev[nl > 0 ? nl : 1];
     if (nl > 0)
@@ -455,7 +469,12 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
             p.ev = yet->d_ev;
             p.trial_begin = o.trial_begin;
             p.trial_count = o.trial_count;
+            const size_t nwc = ((size_t)pf->n_catalogue + 31) / 32;
             p.otab = pf->d_otab + (int64_t)l * pf->n_catalogue;
+            p.sp_bits = pf->d_sp_bits + (size_t)l * nwc;
+            p.sp_rank = pf->d_sp_rank + (size_t)l * (nwc + 1);
+            p.sp_vals = pf->d_sp_vals + (size_t)l * pf->n_catalogue;
+            p.nnz = pf->h_layers[l].nnz;
             p.n_cat = pf->n_catalogue;
             p.agg_r = pf->h_layers[l].agg_r;
             p.agg_l = pf->h_layers[l].agg_l;
@@ -463,8 +482,8 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
             p.ylt_layers = d_ylt_layers;
             p.ylt_pf = d_ylt_portfolio;
             p.accumulate_pf = l > 0;
-            int64_t waves = (o.trial_count + 3) / 4;
-            int64_t g = waves < (int64_t)ctx->n_cu * 8 ? waves : (int64_t)ctx->n_cu * 8;
+            int64_t blocks = (o.trial_count + 3) / 4;
+            int64_t g = blocks < (int64_t)ctx->n_cu * 16 ? blocks : (int64_t)ctx->n_cu * 16;
             p.grid = (int)(g < 1 ? 1 : g);
             ARA_HIP(ctx, launch_pu(p, o.sum_mode, f64out, s));
         }

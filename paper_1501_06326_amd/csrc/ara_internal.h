@@ -32,7 +32,8 @@ struct LayerDev {
     int64_t otab_base;                   // first entry of the layer's otab[n_cat] (PU), or -1
     uint32_t flags;                      // OR of the row flags of the layer
     int32_t n_rows;
-    int32_t pad[2];
+    int32_t nnz;                         // non-zero entries of otab (PU)
+    int32_t pad;
 };
 
 // Per-ELT record: id (keys the draws) and ELT financial terms.
@@ -101,6 +102,9 @@ struct ara_portfolio {
     uint32_t *d_row_meta;
     double *d_row_lnb;
     float *d_otab;
+    uint32_t *d_sp_bits;       // per layer [nw]: bitmap of the non-zero otab entries
+    uint32_t *d_sp_rank;       // per layer [nw + 1]: set bits before each word
+    float *d_sp_vals;          // per layer [n_cat]: the non-zero otab values, in event order
     void *d_workspace;
     size_t workspace_bytes;
     ara::LayerDev *h_layers;   // host copy

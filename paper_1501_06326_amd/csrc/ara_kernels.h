@@ -13,6 +13,10 @@ struct PuLaunch {
     const int32_t *ev;
     int64_t trial_begin, trial_count;
     const float *otab;          // the layer's per-event occurrence losses [n_cat]
+    const uint32_t *sp_bits;    // its sparse form: bitmap [nw], rank [nw + 1], values [nnz]
+    const uint32_t *sp_rank;
+    const float *sp_vals;
+    int32_t nnz;
     int32_t n_cat;
     float agg_r, agg_l;
     int32_t layer;
@@ -59,6 +63,8 @@ hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, con
                               float *row_cfrac, uint32_t *row_meta, double *row_lnb, float *otab,
                               Status *st, hipStream_t s);
 hipError_t launch_pu(const PuLaunch &p, int mode, bool f64out, hipStream_t s);
+hipError_t launch_build_sparse(const float *otab, int32_t n_cat, uint32_t *bits, uint32_t *rank,
+                               float *vals, LayerDev *d_layer, hipStream_t s);
 hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s);
 hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out,
                                hipStream_t s);

@@ -315,47 +315,125 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
 // ---------------------------------------------------------------------------
 // primary uncertainty: per-event occurrence-loss table, gather-sum per trial
 // ---------------------------------------------------------------------------
-template <int MODE, bool F64OUT, bool LDS_TAB>
-__global__ __launch_bounds__(256) void k_ara_pu(const int64_t *__restrict__ off,
-                                                const int32_t *__restrict__ ev,
-                                                int64_t trial_begin, int64_t trial_count,
-                                                const float *__restrict__ otab, int32_t n_cat,
-                                                float agg_r, float agg_l, int32_t layer,
-                                                void *__restrict__ ylt_layers,
-                                                void *__restrict__ ylt_pf, int32_t accumulate_pf) {
-    extern __shared__ float tab[];
-    const float *T = otab;
-    if (LDS_TAB) {
-        for (int i = threadIdx.x; i < n_cat; i += blockDim.x) tab[i] = otab[i];
-        __syncthreads();
-        T = tab;
+// Sparse form of a layer's otab: bit w*32+i of bits[] set when otab is
+// non-zero, rank[w] = set bits before word w (exclusive scan), vals[] the
+// non-zero values in event order.  Lookup of event E: one LDS word, and for
+// the (rare) non-zero events the rank and the value.
+__global__ void k_sp_bits(const float *__restrict__ otab, int32_t n_cat, uint32_t *__restrict__ bits,
+                          uint32_t *__restrict__ rank) {
+    const int32_t nw = (n_cat + 31) >> 5;
+    for (int32_t w = blockIdx.x * blockDim.x + threadIdx.x; w <= nw; w += gridDim.x * blockDim.x) {
+        uint32_t b = 0;
+        if (w < nw)
+            for (int i = 0; i < 32; ++i) {
+                const int32_t e = w * 32 + i;
+                if (e < n_cat && otab[e] != 0.0f) b |= 1u << i;
+            }
+        if (w < nw) bits[w] = b;
+        rank[w] = __popc(b);
     }
+}
+
+__global__ void k_sp_vals(const float *__restrict__ otab, int32_t n_cat,
+                          const uint32_t *__restrict__ bits, const uint32_t *__restrict__ rank,
+                          float *__restrict__ vals, LayerDev *layer) {
+    const int32_t nw = (n_cat + 31) >> 5;
+    for (int32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
+        uint32_t b = bits[w], r = rank[w];
+        while (b) {
+            const int i = __ffs(b) - 1;
+            vals[r++] = otab[w * 32 + i];
+            b &= b - 1;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) layer->nnz = (int32_t)rank[nw];
+}
+
+struct PuArgs {
+    const int64_t *off;
+    const int32_t *ev;
+    int64_t trial_begin, trial_count;
+    const float *otab;
+    const uint32_t *sp_bits, *sp_rank;
+    const float *sp_vals;
+    int32_t nnz, n_cat;
+    float agg_r, agg_l;
+    int32_t layer;
+    void *ylt_layers, *ylt_pf;
+    int32_t accumulate_pf;
+};
+
+enum { TAB_GLOBAL = 0, TAB_LDS_DENSE = 1, TAB_LDS_SPARSE = 2 };
+
+// One wavefront per trial (persistent grid-stride over trials).  Event ids
+// are streamed with 16-byte loads (after a scalar head that reaches 16-byte
+// alignment), four loads in flight per lane.
+template <int MODE, bool F64OUT, int TAB>
+__global__ __launch_bounds__(256) void k_ara_pu(PuArgs P) {
+    extern __shared__ uint32_t sm[];
+    const int32_t nw = (P.n_cat + 31) >> 5;
+    float *tab = (float *)sm;
+    uint32_t *bits = sm, *rank = sm + nw;
+    float *vals = (float *)(sm + 2 * nw + 1);
+    if (TAB == TAB_LDS_DENSE) {
+        for (int i = threadIdx.x; i < P.n_cat; i += blockDim.x) tab[i] = P.otab[i];
+    } else if (TAB == TAB_LDS_SPARSE) {
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) bits[i] = P.sp_bits[i];
+        for (int i = threadIdx.x; i <= nw; i += blockDim.x) rank[i] = P.sp_rank[i];
+        for (int i = threadIdx.x; i < P.nnz; i += blockDim.x) vals[i] = P.sp_vals[i];
+    }
+    if (TAB != TAB_GLOBAL) __syncthreads();
+    auto look = [&](int32_t E) -> float {
+        if (TAB == TAB_GLOBAL) return P.otab[E];
+        if (TAB == TAB_LDS_DENSE) return tab[E];
+        const uint32_t w = bits[E >> 5];
+        const uint32_t m = 1u << (E & 31);
+        return (w & m) ? vals[rank[E >> 5] + __popc(w & (m - 1u))] : 0.0f;
+    };
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t t = wid; t < trial_count; t += nw) {
-        const int64_t a = off[trial_begin + t], b = off[trial_begin + t + 1];
+    const int64_t nwv = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t t = wid; t < P.trial_count; t += nwv) {
+        const int64_t a = P.off[P.trial_begin + t], b = P.off[P.trial_begin + t + 1];
+        const int64_t n = b - a;
         Acc<MODE> acc;
-        for (int64_t j = a + lane; j < b; j += 64) acc.add(T[ev[j]]);
+        // int32 elements up to the next 16-byte boundary of the event-id stream
+        int64_t head = (int64_t)(((16u - ((uint32_t)(uintptr_t)(P.ev + a) & 15u)) & 15u) >> 2);
+        if (head > n) head = n;
+        if (lane < head) acc.add(look(P.ev[a + lane]));
+        const int4 *v4 = (const int4 *)(P.ev + a + head);
+        const int64_t n4 = (n - head) >> 2;
+        for (int64_t i = lane; i < n4; i += 4 * 64) {
+            const bool h1 = i + 64 < n4, h2 = i + 128 < n4, h3 = i + 192 < n4;
+            const int4 q0 = v4[i];
+            int4 q1 = make_int4(0, 0, 0, 0), q2 = q1, q3 = q1;
+            if (h1) q1 = v4[i + 64];
+            if (h2) q2 = v4[i + 128];
+            if (h3) q3 = v4[i + 192];
+            acc.add(look(q0.x)); acc.add(look(q0.y)); acc.add(look(q0.z)); acc.add(look(q0.w));
+            if (h1) { acc.add(look(q1.x)); acc.add(look(q1.y)); acc.add(look(q1.z)); acc.add(look(q1.w)); }
+            if (h2) { acc.add(look(q2.x)); acc.add(look(q2.y)); acc.add(look(q2.z)); acc.add(look(q2.w)); }
+            if (h3) { acc.add(look(q3.x)); acc.add(look(q3.y)); acc.add(look(q3.z)); acc.add(look(q3.w)); }
+        }
+        const int64_t done = head + 4 * n4;
+        if (lane < n - done) acc.add(look(P.ev[a + done + lane]));
         const double S = acc.total();
         if (lane == 0) {
             double Y;
-            if (MODE == ARA_SUM_NAIVE32 || MODE == ARA_SUM_KAHAN32) {
-                Y = (double)clampf_terms((float)S, agg_r, agg_l);
-            } else {
-                Y = clampd_terms(S, (double)agg_r, (double)agg_l);
-            }
+            if (MODE == ARA_SUM_F64) Y = clampd_terms(S, (double)P.agg_r, (double)P.agg_l);
+            else Y = (double)clampf_terms((float)S, P.agg_r, P.agg_l);
             if (F64OUT) {
-                if (ylt_layers) ((double *)ylt_layers)[(int64_t)layer * trial_count + t] = Y;
-                if (ylt_pf) {
-                    double *p = (double *)ylt_pf + t;
-                    *p = accumulate_pf ? *p + Y : Y;
+                if (P.ylt_layers) ((double *)P.ylt_layers)[(int64_t)P.layer * P.trial_count + t] = Y;
+                if (P.ylt_pf) {
+                    double *p = (double *)P.ylt_pf + t;
+                    *p = P.accumulate_pf ? *p + Y : Y;
                 }
             } else {
-                if (ylt_layers) ((float *)ylt_layers)[(int64_t)layer * trial_count + t] = (float)Y;
-                if (ylt_pf) {
-                    float *p = (float *)ylt_pf + t;
-                    *p = accumulate_pf ? *p + (float)Y : (float)Y;
+                if (P.ylt_layers)
+                    ((float *)P.ylt_layers)[(int64_t)P.layer * P.trial_count + t] = (float)Y;
+                if (P.ylt_pf) {
+                    float *p = (float *)P.ylt_pf + t;
+                    *p = P.accumulate_pf ? *p + (float)Y : (float)Y;
                 }
             }
         }
@@ -707,24 +785,39 @@ hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, con
     return hipGetLastError();
 }
 
+hipError_t launch_build_sparse(const float *otab, int32_t n_cat, uint32_t *bits, uint32_t *rank,
+                               float *vals, LayerDev *d_layer, hipStream_t s) {
+    const int32_t nw = (n_cat + 31) >> 5;
+    hipLaunchKernelGGL(k_sp_bits, dim3(grid_for((int64_t)nw + 1, 256)), dim3(256), 0, s, otab, n_cat,
+                       bits, rank);
+    hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, rank, (int64_t)nw + 1);
+    hipLaunchKernelGGL(k_sp_vals, dim3(grid_for(nw, 256)), dim3(256), 0, s, otab, n_cat, bits, rank,
+                       vals, d_layer);
+    return hipGetLastError();
+}
+
 template <int MODE, bool F64OUT>
 static hipError_t pu_dispatch(const PuLaunch &p, hipStream_t s) {
-    const int block = 256;
-    const size_t lds = (size_t)p.n_cat * sizeof(float);
-    const bool use_lds = lds <= 64 * 1024;
-    int g = p.grid;
-    if (use_lds)
-        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, true>), dim3(g), dim3(block), lds, s, p.off,
-                           p.ev, p.trial_begin, p.trial_count, p.otab, p.n_cat, p.agg_r, p.agg_l,
-                           p.layer, p.ylt_layers, p.ylt_pf, p.accumulate_pf);
+    PuArgs A;
+    A.off = p.off; A.ev = p.ev; A.trial_begin = p.trial_begin; A.trial_count = p.trial_count;
+    A.otab = p.otab; A.sp_bits = p.sp_bits; A.sp_rank = p.sp_rank; A.sp_vals = p.sp_vals;
+    A.nnz = p.nnz; A.n_cat = p.n_cat; A.agg_r = p.agg_r; A.agg_l = p.agg_l; A.layer = p.layer;
+    A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf; A.accumulate_pf = p.accumulate_pf;
+    const size_t nw = ((size_t)p.n_cat + 31) / 32;
+    const size_t dense = (size_t)p.n_cat * sizeof(float);
+    const size_t sparse = (2 * nw + 1 + (size_t)p.nnz) * sizeof(uint32_t);
+    const dim3 g(p.grid), b(256);
+    if (dense <= 32 * 1024)
+        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, TAB_LDS_DENSE>), g, b, dense, s, A);
+    else if (sparse <= 60 * 1024)
+        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, TAB_LDS_SPARSE>), g, b, sparse, s, A);
     else
-        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, false>), dim3(g), dim3(block), 0, s, p.off,
-                           p.ev, p.trial_begin, p.trial_count, p.otab, p.n_cat, p.agg_r, p.agg_l,
-                           p.layer, p.ylt_layers, p.ylt_pf, p.accumulate_pf);
+        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, TAB_GLOBAL>), g, b, 0, s, A);
     return hipGetLastError();
 }
 
 hipError_t launch_pu(const PuLaunch &p, int mode, bool f64out, hipStream_t s) {
+    if (p.trial_count <= 0) return hipSuccess;
     if (mode == ARA_SUM_NAIVE32) return f64out ? pu_dispatch<ARA_SUM_NAIVE32, true>(p, s)
                                                : pu_dispatch<ARA_SUM_NAIVE32, false>(p, s);
     if (mode == ARA_SUM_KAHAN32) return f64out ? pu_dispatch<ARA_SUM_KAHAN32, true>(p, s)

@@ -17,7 +17,7 @@ namespace ara {
 // (PhiloxKeys) and the device only runs the rounds.
 // ---------------------------------------------------------------------------
 struct PhiloxKeys {
-    uint32_t k0[10], k1[10];
+    uint32_t k0, k1;           // the key; round r uses (k0 + r W0, k1 + r W1)
 };
 
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
@@ -27,45 +27,47 @@ constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
 inline PhiloxKeys philox_keys(uint64_t seed) {
     PhiloxKeys k;
-    uint32_t a = (uint32_t)seed, b = (uint32_t)(seed >> 32);
-    for (int r = 0; r < 10; ++r) {
-        k.k0[r] = a;
-        k.k1[r] = b;
-        a += kPhiloxW0;
-        b += kPhiloxW1;
-    }
+    k.k0 = (uint32_t)seed;
+    k.k1 = (uint32_t)(seed >> 32);
     return k;
 }
 
+// The key is wave-uniform, so its schedule runs on the scalar unit.
 __device__ __forceinline__ uint4 philox10(uint4 c, const PhiloxKeys &k) {
+    uint32_t k0 = k.k0, k1 = k.k1;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         uint64_t p0 = (uint64_t)kPhiloxM0 * (uint64_t)c.x;
         uint64_t p1 = (uint64_t)kPhiloxM1 * (uint64_t)c.z;
         uint4 n;
-        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k.k0[r];
+        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
         n.y = (uint32_t)p1;
-        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k.k1[r];
+        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
         n.w = (uint32_t)p0;
         c = n;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
     }
     return c;
 }
 
 // Word 0 only: the last round's x output needs only the product M1 * c.z.
 __device__ __forceinline__ uint32_t philox10_x0(uint4 c, const PhiloxKeys &k) {
+    uint32_t k0 = k.k0, k1 = k.k1;
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         uint64_t p0 = (uint64_t)kPhiloxM0 * (uint64_t)c.x;
         uint64_t p1 = (uint64_t)kPhiloxM1 * (uint64_t)c.z;
         uint4 n;
-        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k.k0[r];
+        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
         n.y = (uint32_t)p1;
-        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k.k1[r];
+        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
         n.w = (uint32_t)p0;
         c = n;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
     }
-    return __umulhi(kPhiloxM1, c.z) ^ c.y ^ k.k0[9];
+    return __umulhi(kPhiloxM1, c.z) ^ c.y ^ k0;
 }
 
 // Odd multiple of 2^-24: u = ((w >> 8) | 1) * 2^-24, so 1 - u is exact too.
@@ -77,13 +79,19 @@ __device__ __forceinline__ uint32_t u24(uint32_t w) { return (w >> 8) | 1u; }
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// log2(1 + v) for v > -1, the rounding of w = 1 + v corrected by v / (w - 1)
-// (the classical log1p construction); hardware log2 elsewhere.
-__device__ __forceinline__ float log2_1p(float v) {
-    float w = 1.0f + v;
-    float d = w - 1.0f;
-    float l = __log2f(w);
-    return d == 0.0f ? v * 1.4426950408889634f : l * (v / d);
+// Reciprocal with one Newton step (about 0.5 ulp): cheaper than an IEEE
+// division where the last half ulp does not matter.
+__device__ __forceinline__ float rcp_nr(float y) {
+    const float r = rcp_f(y);
+    return r * fmaf(-y, r, 2.0f);
+}
+
+// log2(1 - x) for 0 <= x < 1: w = 1 - x rounds, but its rounding error
+// e = (1 - w) - x is exact (Fast2Sum, |1| >= |x|), and
+// log2(1 - x) = log2(w) + log2(1 + e/w) ~ log2(w) + (e/w) log2(e).
+__device__ __forceinline__ float log2_1m(float x, float w) {
+    const float e = (1.0f - w) - x;
+    return fmaf(e * rcp_f(w), 1.4426950408889634f, __log2f(w));
 }
 
 // Continued fraction of DLMF 8.17.22: I_x(a, b) = x^a (1-x)^b / (a B(a,b)) / K
@@ -92,37 +100,34 @@ __device__ __forceinline__ float log2_1p(float v) {
 //   d_{2m}   =  m(b-m) x / ((a+2m-1)(a+2m)).
 // Evaluated backward from term n (more accurate in FP32 than the forward
 // recurrence) without divisions: with d_j = p_j / q_j and K_j = N_j / D_j,
-// N_j = q_j N_{j+1} + p_j D_{j+1}, D_j = q_j N_{j+1}; rescaled every four
-// terms.  n comes from the row (enough terms at the slowest point of the
-// branch, see cf_terms); lanes with fewer terms join the loop late.
-// Returns 1/K.
-__device__ __forceinline__ float beta_cf32(float a, float b, float x, int n, int nmax) {
+// N_j = q_j N_{j+1} + p_j D_{j+1}, D_j = q_j N_{j+1}.  Terms go in pairs
+// (2m, 2m-1) with no branches; n (even) comes from the row (enough terms at
+// the slowest point of the branch, see cf_terms); lanes with fewer terms
+// than the batch maximum nmax (even, wave-uniform) leave their (N, D) at the
+// start value until their first term.  Rescaled every pair.  Returns N, D.
+__device__ __forceinline__ void beta_cf32(float a, float b, float x, int n, int nmax, float *Nout,
+                                          float *Dout) {
     float N = 1.0f, D = 1.0f;
     const float apb = a + b;
-    for (int j = nmax; j >= 1; --j) {
-        const int m = j >> 1;
+    for (int m = nmax >> 1; m >= 1; --m) {
         const float fm = (float)m;
-        float t, p;
-        if (j & 1) {
-            t = a + 2.0f * fm;
-            p = -(a + fm) * (apb + fm) * x;
-        } else {
-            t = a + (2.0f * fm - 1.0f);
-            p = fm * (b - fm) * x;
-        }
-        const float q = t * (t + 1.0f);
-        if (j <= n) {
-            const float Nn = q * N + p * D;
-            D = q * N;
-            N = Nn;
-        }
-        if ((j & 3) == 0) {
-            const float s = rcp_f(N);
-            N *= s;
-            D *= s;
-        }
+        // even term 2m: p = m (b - m) x, q = (a + 2m - 1)(a + 2m)
+        const float te = a + (2.0f * fm - 1.0f);
+        const float qe = te * (te + 1.0f);
+        const float pe = fm * (b - fm) * x;
+        // odd term 2m-1 (= 2(m-1)+1): p = -(a+m-1)(a+b+m-1) x, q = (a+2m-2)(a+2m-1)
+        const float to = te - 1.0f;
+        const float qo = to * te;
+        const float po = -(a + (fm - 1.0f)) * (apb + (fm - 1.0f)) * x;
+        const bool on = 2 * m <= n;
+        const float N1 = fmaf(qe, N, pe * D), D1 = qe * N;
+        const float N2 = fmaf(qo, N1, po * D1), D2 = qo * N1;
+        const float s = rcp_f(N2);
+        N = on ? 1.0f : N;
+        D = on ? D2 * s : D;
     }
-    return D / N;
+    *Nout = N;
+    *Dout = D;
 }
 
 // Terms of the continued fraction that FP32 needs (truncation below 1e-8
@@ -151,35 +156,36 @@ __device__ inline int cf_terms(double a, double b) {
 // deviate y of the smaller tail probability, then A&S 26.5.22 for the Beta
 // quantile (valid for a, b > 1/2; used here for a, b >= 1).
 __device__ __forceinline__ float beta_guess32(float a, float b, float z, float zc) {
+    // only a starting point: approximate reciprocals are enough
     const bool lowz = z < 0.5f;
     const float pp = lowz ? z : zc;
     const float t = sqrtf(-2.0f * __logf(pp));
-    float y = t - (2.30753f + 0.27061f * t) / (1.0f + t * (0.99229f + 0.04481f * t));
+    float y = t - (2.30753f + 0.27061f * t) * rcp_f(1.0f + t * (0.99229f + 0.04481f * t));
     if (!lowz) y = -y;                       // y = Phi^-1(1 - z)
-    const float lam = (y * y - 3.0f) / 6.0f;
-    const float ra = 1.0f / (2.0f * a - 1.0f), rb = 1.0f / (2.0f * b - 1.0f);
-    const float h = 2.0f / (ra + rb);
-    const float w = y * sqrtf(h + lam) / h - (rb - ra) * (lam + 5.0f / 6.0f - 2.0f / (3.0f * h));
-    return a / (a + b * __expf(2.0f * w));
+    const float lam = (y * y - 3.0f) * (1.0f / 6.0f);
+    const float ra = rcp_f(2.0f * a - 1.0f), rb = rcp_f(2.0f * b - 1.0f);
+    const float rh = 0.5f * (ra + rb);       // 1 / h, h = 2 / (ra + rb)
+    const float w = y * sqrtf(rcp_f(rh) + lam) * rh -
+                    (rb - ra) * (lam + 5.0f / 6.0f - (2.0f / 3.0f) * rh);
+    return a * rcp_f(a + b * __expf(2.0f * w));
 }
 
 // I_x(a,b) (*I) and 1 - I_x(a,b) (*Ic), each on the side where it is
 // accurate, and the Beta density at x; lnb2 = log2 B(a, b); na / nb the
-// continued-fraction terms of the (a, b) and (b, a) branches.
-__device__ __forceinline__ void beta_inc32(float a, float b, float lnb2, int na, int nb, float x,
-                                           float *I, float *Ic, float *dens) {
+// continued-fraction terms of the (a, b) and (b, a) branches; nmax the
+// wave-uniform bound of both.
+__device__ __forceinline__ void beta_inc32(float a, float b, float lnb2, int na, int nb, int nmax,
+                                           float x, float *I, float *Ic, float *dens) {
     const float w = 1.0f - x;
-    const float e2 = a * __log2f(x) + (b * log2_1p(-x) - lnb2);
+    const float e2 = fmaf(a, __log2f(x), fmaf(b, log2_1m(x, w), -lnb2));
     const float front = exp2f(e2);           // x^a (1-x)^b / B(a,b)
-    *dens = front / (x * w);
+    *dens = front * rcp_f(x * w);
     const bool direct = x * (a + b + 2.0f) < a + 1.0f;
-    // both branches in one loop: (a, b, x) directly, else (b, a, 1 - x)
+    // one loop for both branches: (a, b, x) directly, else (b, a, 1 - x)
     const float A = direct ? a : b, B = direct ? b : a, X = direct ? x : w;
-    const int n = direct ? na : nb;
-    int nmax = n;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, __shfl_xor(nmax, d, 64));
-    const float v = front * beta_cf32(A, B, X, n, nmax) / A;
+    float N, D;
+    beta_cf32(A, B, X, direct ? na : nb, nmax, &N, &D);
+    const float v = front * D * rcp_nr(N * A);
     *I = direct ? v : 1.0f - v;
     *Ic = direct ? 1.0f - v : v;
 }
@@ -188,8 +194,11 @@ __device__ __forceinline__ void beta_inc32(float a, float b, float lnb2, int na,
 // shapes inside the FP32 domain (kF32MinShape <= a, b <= kF32MaxShape).
 // Halley iterations on the side where the root is at most ~1/2 (mirroring
 // through I_{1-x}(b,a) = 1 - z otherwise), with the residual taken on the
-// side of the smaller of z, zc so it never cancels.  Returns false in *ok if
-// it did not converge (the caller then uses the FP64 path).
+// side of the smaller of z, zc so it never cancels; the step sizes use
+// reciprocals (they only set the speed, the residual sets the root).  Stops
+// when every lane's last step was below 2^-10 of the root (Halley: the next
+// error ~ step^3).  Returns false in *ok if it did not converge (the caller
+// then uses the FP64 path).
 __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, int na, int nb,
                                                  float z, float zc, bool *ok) {
     float x0 = beta_guess32(a, b, z, zc);
@@ -200,20 +209,28 @@ __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, i
         A = b; B = a; Z = zc; ZC = z; NA = nb; NB = na;
         x0 = 1.0f - x0;
     }
+    // bound of both branches' term counts over the active lanes only (a
+    // shuffle would also read the registers of inactive lanes): bitwise
+    // maximum by ballots, counts are below 64
+    const int nl = max(na, nb);
+    int nmax = 0;
+#pragma unroll
+    for (int bit = 32; bit >= 1; bit >>= 1)
+        if (__any(nl >= (nmax | bit))) nmax |= bit;
     float x = fminf(fmaxf(x0, 1e-30f), 0.75f);
     const bool lower = Z <= 0.5f;
     bool conv = false;
     for (int it = 0; it < 6; ++it) {
         float I, Ic, dens;
-        beta_inc32(A, B, lnb2, NA, NB, x, &I, &Ic, &dens);
+        beta_inc32(A, B, lnb2, NA, NB, nmax, x, &I, &Ic, &dens);
         const float r = lower ? (I - Z) : (ZC - Ic);
-        const float u = r / dens;
+        const float u = r * rcp_f(dens);
         const float hh = (A - 1.0f) * rcp_f(x) - (B - 1.0f) * rcp_f(1.0f - x);
-        const float t = u / (1.0f - 0.5f * fminf(1.0f, u * hh));
+        const float t = u * rcp_f(1.0f - 0.5f * fminf(1.0f, u * hh));
         float xn = x - t;
         if (!(xn > 0.0f)) xn = 0.5f * x;
         if (!(xn < 1.0f)) xn = 0.5f * (x + 1.0f);
-        conv = fabsf(xn - x) <= 6.1e-5f * xn;   // Halley: the next error ~ step^3
+        conv = fabsf(xn - x) <= 9.765625e-4f * xn;
         x = xn;
         if (__all(conv)) break;
     }
