@@ -178,6 +178,50 @@ ara_status ara_run_scratch_size(int64_t trial_count, size_t *bytes);
  * hit a non-converging quantile; clears the flag. */
 ara_status ara_sync_status(ara_context *ctx, void *stream);
 
+/* ---- batched portfolios --------------------------------------------------
+ * Several portfolios (Algorithm 1's outer portfolio / program loops) over one
+ * YET in one persistent launch: work items are (tile of trial_tile trials,
+ * portfolio), taken trial-major from an atomic counter so that the
+ * portfolios of one tile run close together and reuse its event ids from
+ * cache.  Results are bit-identical to running each portfolio alone with
+ * ara_run.  d_ylt_layers / d_ylt_portfolio are host arrays of n_portfolios
+ * device pointers (entries may be NULL), laid out as for ara_run over
+ * opts->trial_count trials.  opts->d_hits / d_hit_chk must be NULL; its
+ * d_scratch is not used (the batch scratch is the explicit argument,
+ * ara_batch_scratch_size bytes).  cfg = NULL: trial_tile 4, 16 waves per CU. */
+typedef struct {
+    int32_t trial_tile;         /* trials per work item (>= 1) */
+    int32_t waves_per_cu;       /* resident wavefronts per compute unit (>= 1) */
+} ara_batch_config;
+
+ara_status ara_batch_scratch_size(int32_t n_portfolios, int64_t trial_count, size_t *bytes);
+ara_status ara_run_batch(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
+                         ara_portfolio *const *pfs, const ara_run_opts *opts,
+                         const ara_batch_config *cfg, void *const *d_ylt_layers,
+                         void *const *d_ylt_portfolio, void *d_scratch, size_t scratch_bytes,
+                         void *stream);
+
+/* Autotuner: times ara_run_batch over opts' trial range for trial tiles
+ * {1, 2, 4, 8} x {8, 12, 16, 20} waves per CU (HIP events, after one warmup)
+ * and returns the fastest configuration and its time.  Synchronises. */
+ara_status ara_batch_autotune(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
+                              ara_portfolio *const *pfs, const ara_run_opts *opts,
+                              void *const *d_ylt_layers, void *const *d_ylt_portfolio,
+                              void *d_scratch, size_t scratch_bytes, void *stream,
+                              ara_batch_config *best, double *best_ms);
+
+/* The same batched run captured once in a HIP graph (no host work between
+ * replays); the graph keeps the pointers it was built with, which must stay
+ * valid while it exists.  ara_graph_launch replays it on the stream. */
+typedef struct ara_graph ara_graph;
+ara_status ara_batch_graph_create(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
+                                  ara_portfolio *const *pfs, const ara_run_opts *opts,
+                                  const ara_batch_config *cfg, void *const *d_ylt_layers,
+                                  void *const *d_ylt_portfolio, void *d_scratch,
+                                  size_t scratch_bytes, ara_graph **out);
+ara_status ara_graph_launch(ara_context *ctx, ara_graph *graph, void *stream);
+ara_status ara_graph_destroy(ara_context *ctx, ara_graph *graph);
+
 /* ---- risk metrics (section 2.3) -------------------------------------------
  * PML and TVaR of the n losses in d_ylt (ARA_F32 or ARA_F64, all >= 0) for
  * n_rp return periods; results to host arrays pml_out / tvar_out.  The k-th

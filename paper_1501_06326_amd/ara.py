@@ -38,7 +38,9 @@ EXPORTS = ["ara_create", "ara_destroy", "ara_status_string", "ara_last_error", "
            "ara_free_yet", "ara_portfolio_workspace_size", "ara_load_portfolio",
            "ara_free_portfolio", "ara_run", "ara_run_scratch_size", "ara_sync_status",
            "ara_pml_tvar_scratch_size", "ara_pml_tvar", "ara_debug_philox",
-           "ara_debug_beta_quantile"]
+           "ara_debug_beta_quantile", "ara_batch_scratch_size", "ara_run_batch",
+           "ara_batch_autotune", "ara_batch_graph_create", "ara_graph_launch",
+           "ara_graph_destroy"]
 
 
 class AraError(RuntimeError):
@@ -64,6 +66,10 @@ class ara_layer_desc(C.Structure):
 class ara_portfolio_desc(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("layers", C.POINTER(ara_layer_desc)),
                 ("seed", C.c_uint64), ("su_enabled", C.c_int32)]
+
+
+class ara_batch_config(C.Structure):
+    _fields_ = [("trial_tile", C.c_int32), ("waves_per_cu", C.c_int32)]
 
 
 class ara_run_opts(C.Structure):
@@ -107,6 +113,17 @@ def lib():
         L.ara_pml_tvar.argtypes = [p, p, i32, i64, p, i32, p, p, p, sz, p]
         L.ara_debug_philox.argtypes = [p, i64, p, u64, p, p]
         L.ara_debug_beta_quantile.argtypes = [p, i64, p, p, p, p, C.c_float, p, p, p]
+        pp = C.POINTER(C.c_void_p)
+        L.ara_batch_scratch_size.argtypes = [i32, i64, C.POINTER(sz)]
+        L.ara_run_batch.argtypes = [p, p, i32, pp, C.POINTER(ara_run_opts),
+                                    C.POINTER(ara_batch_config), pp, pp, p, sz, p]
+        L.ara_batch_autotune.argtypes = [p, p, i32, pp, C.POINTER(ara_run_opts), pp, pp, p, sz, p,
+                                         C.POINTER(ara_batch_config), C.POINTER(C.c_double)]
+        L.ara_batch_graph_create.argtypes = [p, p, i32, pp, C.POINTER(ara_run_opts),
+                                             C.POINTER(ara_batch_config), pp, pp, p, sz,
+                                             C.POINTER(p)]
+        L.ara_graph_launch.argtypes = [p, p, p]
+        L.ara_graph_destroy.argtypes = [p, p]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is C.c_int:       # default
@@ -220,6 +237,61 @@ def ara_debug_beta_quantile(ctx, n: int, d_a: int, d_b: int, d_z: int, d_zc: int
                             stream: Optional[int]):
     _check(ctx, lib().ara_debug_beta_quantile(ctx, int(n), d_a, d_b, d_z, d_zc, float(tail_band),
                                               d_x, d_path, stream), "ara_debug_beta_quantile")
+
+
+def _ptr_array(vals):
+    arr = (C.c_void_p * max(1, len(vals)))()
+    for i, v in enumerate(vals):
+        arr[i] = v
+    return arr
+
+
+def ara_batch_scratch_size(n_portfolios: int, trial_count: int) -> int:
+    n = C.c_size_t()
+    rc = lib().ara_batch_scratch_size(int(n_portfolios), int(trial_count), C.byref(n))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_batch_scratch_size")
+    return int(n.value)
+
+
+def ara_run_batch(ctx, yet, pfs, opts: "ara_run_opts", cfg: Optional["ara_batch_config"],
+                  d_ylt_layers, d_ylt_portfolio, d_scratch: int, scratch_bytes: int,
+                  stream: Optional[int]) -> None:
+    _check(ctx, lib().ara_run_batch(ctx, yet, len(pfs), _ptr_array(pfs), C.byref(opts),
+                                    C.byref(cfg) if cfg is not None else None,
+                                    _ptr_array(d_ylt_layers), _ptr_array(d_ylt_portfolio),
+                                    d_scratch, int(scratch_bytes), stream), "ara_run_batch")
+
+
+def ara_batch_autotune(ctx, yet, pfs, opts: "ara_run_opts", d_ylt_layers, d_ylt_portfolio,
+                       d_scratch: int, scratch_bytes: int, stream: Optional[int]):
+    best = ara_batch_config()
+    ms = C.c_double()
+    _check(ctx, lib().ara_batch_autotune(ctx, yet, len(pfs), _ptr_array(pfs), C.byref(opts),
+                                         _ptr_array(d_ylt_layers), _ptr_array(d_ylt_portfolio),
+                                         d_scratch, int(scratch_bytes), stream, C.byref(best),
+                                         C.byref(ms)), "ara_batch_autotune")
+    return best, float(ms.value)
+
+
+def ara_batch_graph_create(ctx, yet, pfs, opts: "ara_run_opts", cfg: Optional["ara_batch_config"],
+                           d_ylt_layers, d_ylt_portfolio, d_scratch: int, scratch_bytes: int):
+    h = C.c_void_p()
+    _check(ctx, lib().ara_batch_graph_create(ctx, yet, len(pfs), _ptr_array(pfs), C.byref(opts),
+                                             C.byref(cfg) if cfg is not None else None,
+                                             _ptr_array(d_ylt_layers),
+                                             _ptr_array(d_ylt_portfolio), d_scratch,
+                                             int(scratch_bytes), C.byref(h)),
+           "ara_batch_graph_create")
+    return h
+
+
+def ara_graph_launch(ctx, graph, stream: Optional[int]) -> None:
+    _check(ctx, lib().ara_graph_launch(ctx, graph, stream), "ara_graph_launch")
+
+
+def ara_graph_destroy(ctx, graph) -> None:
+    _check(ctx, lib().ara_graph_destroy(ctx, graph), "ara_graph_destroy")
 
 
 def _ptr(t) -> Optional[int]:
@@ -396,6 +468,70 @@ class Ara:
         dtype = ARA_F64 if y.dtype == t.float64 else ARA_F32
         return ara_pml_tvar(self.ctx, _ptr(y), dtype, n, return_periods, _ptr(scratch), sz,
                             _stream_handle(stream))
+
+    # -- batched portfolios -----------------------------------------------------
+    def _batch_setup(self, y, pfs, trial_begin, trial_count, sum_mode, ylt_dtype, tail_band,
+                     outs):
+        t = self.torch
+        if trial_count is None:
+            trial_count = y.n_trials - trial_begin
+        dt = t.float64 if ylt_dtype == "f64" else t.float32
+        if outs is None:
+            outs = [{"ylt": t.empty((p.n_layers, trial_count), dtype=dt, device=self.device),
+                     "ylt_pf": t.empty(trial_count, dtype=dt, device=self.device)} for p in pfs]
+        n = ara_batch_scratch_size(len(pfs), trial_count)
+        scratch = t.empty(n, dtype=t.uint8, device=self.device)
+        o = ara_run_opts(trial_begin=int(trial_begin), trial_count=int(trial_count),
+                         sum_mode=SUM_MODES[sum_mode],
+                         ylt_dtype=ARA_F64 if ylt_dtype == "f64" else ARA_F32,
+                         tail_band=float(tail_band), reserved=0, d_hits=None, d_hit_chk=None,
+                         d_scratch=None, scratch_bytes=0)
+        return o, outs, scratch
+
+    def run_batch(self, y, pfs, trial_begin=0, trial_count=None, sum_mode="naive32",
+                  ylt_dtype="f32", tail_band=0.0, cfg=None, outs=None, stream=None, sync=True,
+                  scratch=None):
+        """One persistent launch over several DevicePortfolio; returns a list of
+        {"ylt", "ylt_pf"} device tensors, one per portfolio."""
+        o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, sum_mode, ylt_dtype,
+                                        tail_band, outs)
+        if scratch is not None:
+            sc = scratch
+        c = None if cfg is None else ara_batch_config(*cfg)
+        s = _stream_handle(stream)
+        ara_run_batch(self.ctx, y.handle, [p.handle.value for p in pfs], o, c,
+                      [_ptr(r["ylt"]) for r in outs], [_ptr(r["ylt_pf"]) for r in outs],
+                      _ptr(sc), sc.numel(), s)
+        if sync:
+            ara_sync_status(self.ctx, s)
+        return outs
+
+    def batch_autotune(self, y, pfs, trial_begin=0, trial_count=4096, stream=None):
+        o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, "naive32", "f32", 0.0,
+                                        None)
+        best, ms = ara_batch_autotune(self.ctx, y.handle, [p.handle.value for p in pfs], o,
+                                      [_ptr(r["ylt"]) for r in outs],
+                                      [_ptr(r["ylt_pf"]) for r in outs], _ptr(sc), sc.numel(),
+                                      _stream_handle(stream))
+        return (best.trial_tile, best.waves_per_cu), ms
+
+    def batch_graph(self, y, pfs, trial_begin=0, trial_count=None, sum_mode="naive32",
+                    ylt_dtype="f32", cfg=None):
+        """Capture the batched run in a HIP graph; returns (graph handle, outs,
+        scratch); keep outs and scratch alive while the graph exists."""
+        o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, sum_mode, ylt_dtype,
+                                        0.0, None)
+        c = None if cfg is None else ara_batch_config(*cfg)
+        g = ara_batch_graph_create(self.ctx, y.handle, [p.handle.value for p in pfs], o, c,
+                                   [_ptr(r["ylt"]) for r in outs],
+                                   [_ptr(r["ylt_pf"]) for r in outs], _ptr(sc), sc.numel())
+        return g, outs, sc
+
+    def graph_launch(self, g, stream=None):
+        ara_graph_launch(self.ctx, g, _stream_handle(stream))
+
+    def graph_destroy(self, g):
+        ara_graph_destroy(self.ctx, g)
 
     # -- diagnostics ------------------------------------------------------------
     def debug_philox(self, ctr, key: int, stream=None):

@@ -27,6 +27,12 @@ struct ara_context {
     size_t run_scratch_bytes = 0;
     std::set<ara_yet *> yets;
     std::set<ara_portfolio *> pfs;
+    std::set<ara_graph *> graphs;
+};
+
+struct ara_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -211,6 +217,11 @@ void ara_destroy(ara_context *ctx) {
     for (ara_portfolio *p : ctx->pfs) {
         delete[] p->h_layers;
         delete p;
+    }
+    for (ara_graph *g : ctx->graphs) {
+        (void)hipGraphExecDestroy(g->exec);
+        (void)hipGraphDestroy(g->graph);
+        delete g;
     }
     (void)hipFree(ctx->d_status);
     (void)hipFree(ctx->d_maxlen);
@@ -581,6 +592,226 @@ ara_status ara_pml_tvar(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, 
         pml_out[r] = h[r];
         tvar_out[r] = h[(size_t)n_rp + r];
     }
+    return ARA_OK;
+}
+
+// ---- batched portfolios ----------------------------------------------------
+namespace {
+
+size_t batch_pf_off() { return 256; }
+size_t batch_redo_off(int32_t n) { return align256(batch_pf_off() + sizeof(BatchPf) * (size_t)n); }
+size_t batch_need(int32_t n, int64_t trials) {
+    return batch_redo_off(n) + sizeof(unsigned long long) * (size_t)n * (size_t)(trials > 0 ? trials : 1);
+}
+
+struct BatchPlan {
+    BatchArgs B;
+    int grid, redo_grid, mode;
+    bool f64out;
+};
+
+ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portfolio *const *pfs,
+                      const ara_run_opts *opts, const ara_batch_config *cfg,
+                      void *const *ylt_l, void *const *ylt_p, void *scratch, size_t bytes,
+                      hipStream_t s, BatchPlan *plan) {
+    if (!yet || !ctx->yets.count(const_cast<ara_yet *>(yet)) || n <= 0 || !pfs)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad YET or portfolio list");
+    ara_run_opts o;
+    std::memset(&o, 0, sizeof o);
+    o.trial_count = -1;
+    if (opts) o = *opts;
+    if (o.trial_count < 0) o.trial_count = yet->n_trials - o.trial_begin;
+    if (o.trial_begin < 0 || o.trial_begin + o.trial_count > yet->n_trials ||
+        o.trial_count > 0x7fffffff)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: trial range outside the YET");
+    if (o.sum_mode < ARA_SUM_NAIVE32 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
+        o.ylt_dtype > ARA_F64)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad sum_mode or ylt_dtype");
+    if (o.d_hits || o.d_hit_chk)
+        return fail(ctx, ARA_E_UNSUPPORTED, "ara_run_batch: hit diagnostics are per-portfolio only");
+    if (!(o.tail_band > 0.0f)) o.tail_band = kDefaultTailBand;
+    ara_batch_config c = {4, 16};
+    if (cfg) c = *cfg;
+    if (c.trial_tile < 1 || c.waves_per_cu < 1)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad batch configuration");
+    const size_t need = batch_need(n, o.trial_count);
+    if (!scratch || bytes < need)
+        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_run_batch: need %zu scratch bytes", need);
+    std::vector<BatchPf> h((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const ara_portfolio *p = pfs[i];
+        if (!p || !ctx->pfs.count(const_cast<ara_portfolio *>(p)))
+            return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: unknown portfolio %d", i);
+        if (p->n_catalogue != yet->n_catalogue)
+            return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: portfolio %d catalogue mismatch", i);
+        BatchPf &b = h[(size_t)i];
+        b.layers = p->d_layers;
+        b.elts = p->d_elts;
+        b.evoff = p->d_evoff;
+        b.rowq = p->d_rowq;
+        b.row_mean = p->d_row_mean;
+        b.row_cfrac = p->d_row_cfrac;
+        b.row_meta = p->d_row_meta;
+        b.row_lnb = p->d_row_lnb;
+        b.ylt_layers = ylt_l ? ylt_l[i] : nullptr;
+        b.ylt_pf = ylt_p ? ylt_p[i] : nullptr;
+        b.k0 = (uint32_t)p->seed;
+        b.k1 = (uint32_t)(p->seed >> 32);
+        b.n_layers = p->n_layers;
+        b.pad = 0;
+    }
+    char *sc = (char *)scratch;
+    ARA_HIP(ctx, hipMemcpyAsync(sc + batch_pf_off(), h.data(), sizeof(BatchPf) * h.size(),
+                                hipMemcpyHostToDevice, s));
+    BatchArgs &B = plan->B;
+    B.off = yet->d_off;
+    B.ev = yet->d_ev;
+    B.trial_begin = o.trial_begin;
+    B.trial_count = o.trial_count;
+    B.pfs = (const BatchPf *)(sc + batch_pf_off());
+    B.n_pf = n;
+    B.tile = c.trial_tile;
+    B.tail_band = o.tail_band;
+    B.counter = (unsigned long long *)sc;
+    B.redo_count = (uint32_t *)(sc + 8);
+    B.redo = (unsigned long long *)(sc + batch_redo_off(n));
+    B.status = ctx->d_status;
+    plan->grid = ctx->n_cu * c.waves_per_cu;
+    plan->redo_grid = ctx->n_cu * 4;
+    plan->mode = o.sum_mode;
+    plan->f64out = o.ylt_dtype == ARA_F64;
+    return ARA_OK;
+}
+
+}  // namespace
+
+ara_status ara_batch_scratch_size(int32_t n_portfolios, int64_t trial_count, size_t *bytes) {
+    if (!bytes || n_portfolios <= 0 || trial_count < 0) return ARA_E_INVALID_ARG;
+    *bytes = batch_need(n_portfolios, trial_count);
+    return ARA_OK;
+}
+
+ara_status ara_run_batch(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
+                         ara_portfolio *const *pfs, const ara_run_opts *opts,
+                         const ara_batch_config *cfg, void *const *d_ylt_layers,
+                         void *const *d_ylt_portfolio, void *d_scratch, size_t scratch_bytes,
+                         void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    BatchPlan plan;
+    ara_status st = prep_batch(ctx, yet, n_portfolios, pfs, opts, cfg, d_ylt_layers,
+                               d_ylt_portfolio, d_scratch, scratch_bytes, s, &plan);
+    if (st != ARA_OK) return st;
+    ARA_HIP(ctx, launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s));
+    return ARA_OK;
+}
+
+ara_status ara_batch_autotune(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
+                              ara_portfolio *const *pfs, const ara_run_opts *opts,
+                              void *const *d_ylt_layers, void *const *d_ylt_portfolio,
+                              void *d_scratch, size_t scratch_bytes, void *stream,
+                              ara_batch_config *best, double *best_ms) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!best) return fail(ctx, ARA_E_INVALID_ARG, "ara_batch_autotune: null result");
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    hipEvent_t e0, e1;
+    ARA_HIP(ctx, hipEventCreate(&e0));
+    ARA_HIP(ctx, hipEventCreate(&e1));
+    const int tiles[] = {1, 2, 4, 8};
+    const int waves[] = {8, 12, 16, 20};
+    double bms = 1e300;
+    ara_batch_config bc = {4, 16};
+    ara_status st = ARA_OK;
+    for (int ti = 0; ti < 4 && st == ARA_OK; ++ti)
+        for (int wi = 0; wi < 4 && st == ARA_OK; ++wi) {
+            ara_batch_config c = {tiles[ti], waves[wi]};
+            BatchPlan plan;
+            st = prep_batch(ctx, yet, n_portfolios, pfs, opts, &c, d_ylt_layers, d_ylt_portfolio,
+                            d_scratch, scratch_bytes, s, &plan);
+            if (st != ARA_OK) break;
+            hipError_t he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+            if (he == hipSuccess) he = hipEventRecord(e0, s);
+            if (he == hipSuccess)
+                he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) {
+                st = fail(ctx, ARA_E_HIP, "ara_batch_autotune: %s", hipGetErrorString(he));
+                break;
+            }
+            if (ms < bms) {
+                bms = ms;
+                bc = c;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ARA_OK) return st;
+    *best = bc;
+    if (best_ms) *best_ms = bms;
+    return check_status(ctx, s, "ara_batch_autotune");
+}
+
+ara_status ara_batch_graph_create(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
+                                  ara_portfolio *const *pfs, const ara_run_opts *opts,
+                                  const ara_batch_config *cfg, void *const *d_ylt_layers,
+                                  void *const *d_ylt_portfolio, void *d_scratch,
+                                  size_t scratch_bytes, ara_graph **out) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!out) return fail(ctx, ARA_E_INVALID_ARG, "ara_batch_graph_create: null out");
+    *out = nullptr;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t cap;
+    ARA_HIP(ctx, hipStreamCreate(&cap));
+    BatchPlan plan;
+    // the portfolio table is copied eagerly; the graph holds only kernels
+    ara_status st = prep_batch(ctx, yet, n_portfolios, pfs, opts, cfg, d_ylt_layers,
+                               d_ylt_portfolio, d_scratch, scratch_bytes, cap, &plan);
+    if (st == ARA_OK) {
+        hipError_t he = hipStreamSynchronize(cap);
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (he == hipSuccess) {
+            hipError_t le = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, cap);
+            he = hipStreamEndCapture(cap, &g);
+            if (he == hipSuccess) he = le;
+        }
+        if (he == hipSuccess) he = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (he != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            st = fail(ctx, ARA_E_HIP, "ara_batch_graph_create: %s", hipGetErrorString(he));
+        } else {
+            ara_graph *gr = new ara_graph();
+            gr->graph = g;
+            gr->exec = x;
+            ctx->graphs.insert(gr);
+            *out = gr;
+        }
+    }
+    (void)hipStreamDestroy(cap);
+    return st;
+}
+
+ara_status ara_graph_launch(ara_context *ctx, ara_graph *graph, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!graph || !ctx->graphs.count(graph))
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_graph_launch: unknown graph");
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    ARA_HIP(ctx, hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return ARA_OK;
+}
+
+ara_status ara_graph_destroy(ara_context *ctx, ara_graph *graph) {
+    if (!ctx || !graph || !ctx->graphs.count(graph)) return ARA_E_INVALID_ARG;
+    ctx->graphs.erase(graph);
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    delete graph;
     return ARA_OK;
 }
 

@@ -51,6 +51,37 @@ struct SuLaunch {
     int redo_grid;            // blocks of the second pass
 };
 
+// One portfolio of a batched run (device array of these).
+struct BatchPf {
+    const LayerDev *layers;
+    const EltDev *elts;
+    const uint32_t *evoff;
+    const RowQ *rowq;
+    const float *row_mean;
+    const float *row_cfrac;
+    const uint32_t *row_meta;
+    const double *row_lnb;
+    void *ylt_layers;
+    void *ylt_pf;
+    uint32_t k0, k1;           // Philox key (the portfolio's seed)
+    int32_t n_layers;
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const int64_t *off;
+    const int32_t *ev;
+    int64_t trial_begin, trial_count;
+    const BatchPf *pfs;
+    int32_t n_pf;
+    int32_t tile;                       // trials per work item
+    float tail_band;
+    unsigned long long *counter;        // work-item counter
+    unsigned long long *redo;           // (portfolio << 32 | trial) handed to the FP64 pass
+    uint32_t *redo_count;
+    Status *status;
+};
+
 hipError_t launch_validate_yet(const int64_t *off, const int32_t *ev, const float *times,
                                int64_t n_trials, int32_t n_cat, Status *st,
                                unsigned long long *max_len, hipStream_t s);
@@ -66,6 +97,8 @@ hipError_t launch_pu(const PuLaunch &p, int mode, bool f64out, hipStream_t s);
 hipError_t launch_build_sparse(const float *otab, int32_t n_cat, uint32_t *bits, uint32_t *rank,
                                float *vals, LayerDev *d_layer, hipStream_t s);
 hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s);
+hipError_t launch_batch(const BatchArgs &B, int mode, bool f64out, int grid, int redo_grid,
+                        hipStream_t s);
 hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out,
                                hipStream_t s);
 hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, const double *z,

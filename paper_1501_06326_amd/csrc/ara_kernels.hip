@@ -684,6 +684,87 @@ __global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
 }
 
 // ---------------------------------------------------------------------------
+// batched portfolios: one persistent launch over (trial tile, portfolio)
+// work items, trial-major so the portfolios of one tile run close together
+// and share that tile's event ids from cache; an atomic counter hands out the
+// items (load balance across portfolios of very different cost)
+// ---------------------------------------------------------------------------
+__global__ void k_batch_reset(unsigned long long *counter, uint32_t *redo_count) {
+    *counter = 0ull;
+    *redo_count = 0u;
+}
+
+__global__ void k_reset_u32(uint32_t *p) { *p = 0u; }
+
+__device__ __forceinline__ void batch_view(const BatchArgs &B, int p, SuArgs &A, PhiloxKeys &keys) {
+    const BatchPf &P = B.pfs[p];
+    A.off = B.off;
+    A.ev = B.ev;
+    A.trial_begin = B.trial_begin;
+    A.trial_count = B.trial_count;
+    A.layers = P.layers;
+    A.n_layers = P.n_layers;
+    A.elts = P.elts;
+    A.evoff = P.evoff;
+    A.rowq = P.rowq;
+    A.row_mean = P.row_mean;
+    A.row_cfrac = P.row_cfrac;
+    A.row_meta = P.row_meta;
+    A.row_lnb = P.row_lnb;
+    A.tail_band = B.tail_band;
+    A.ylt_layers = P.ylt_layers;
+    A.ylt_pf = P.ylt_pf;
+    A.hits = nullptr;
+    A.hit_chk = nullptr;
+    A.status = B.status;
+    A.redo = nullptr;
+    A.redo_count = nullptr;
+    keys.k0 = P.k0;
+    keys.k1 = P.k1;
+}
+
+template <int MODE, bool F64OUT>
+__global__ __launch_bounds__(64) void k_ara_batch(BatchArgs B) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    const int lane = threadIdx.x;
+    const int64_t n_tiles = (B.trial_count + B.tile - 1) / B.tile;
+    const unsigned long long n_items = (unsigned long long)n_tiles * (unsigned long long)B.n_pf;
+    while (true) {
+        unsigned long long item = 0;
+        if (lane == 0) item = atomicAdd(B.counter, 1ull);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)item);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(item >> 32));
+        item = ((unsigned long long)hi << 32) | lo;
+        if (item >= n_items) break;
+        const int64_t tile = (int64_t)(item / (unsigned long long)B.n_pf);
+        const int p = (int)(item % (unsigned long long)B.n_pf);
+        SuArgs A;
+        PhiloxKeys keys;
+        batch_view(B, p, A, keys);
+        const int64_t t0 = tile * B.tile;
+        const int64_t t1 = (t0 + B.tile) < B.trial_count ? (t0 + B.tile) : B.trial_count;
+        for (int64_t t = t0; t < t1; ++t)
+            if (su_trial<MODE, F64OUT, false, false>(A, keys, t, X, Q) && lane == 0)
+                B.redo[atomicAdd(B.redo_count, 1u)] = ((unsigned long long)p << 32) | (uint64_t)t;
+    }
+}
+
+template <int MODE, bool F64OUT>
+__global__ __launch_bounds__(64) void k_ara_batch_redo(BatchArgs B) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    const uint32_t n = *B.redo_count;
+    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const unsigned long long e = B.redo[r];
+        SuArgs A;
+        PhiloxKeys keys;
+        batch_view(B, (int)(e >> 32), A, keys);
+        su_trial<MODE, F64OUT, false, true>(A, keys, (int64_t)(e & 0xffffffffull), X, Q);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // diagnostics
 // ---------------------------------------------------------------------------
 __global__ void k_debug_philox(int64_t n, const uint32_t *__restrict__ ctr, PhiloxKeys keys,
@@ -836,8 +917,8 @@ static hipError_t su_dispatch2(const SuLaunch &p, hipStream_t s) {
     A.hits = p.hits; A.hit_chk = p.hit_chk; A.status = p.status;
     A.redo = p.redo; A.redo_count = p.redo_count;
     const PhiloxKeys keys = philox_keys(p.seed);
-    hipError_t e = hipMemsetAsync(p.redo_count, 0, sizeof(uint32_t), s);
-    if (e != hipSuccess) return e;
+    // a kernel, not hipMemsetAsync, so the sequence can be captured in a graph
+    hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(1), 0, s, p.redo_count);
     const dim3 g((unsigned)p.trial_count), gr((unsigned)p.redo_grid);
     if (p.hits || p.hit_chk) {
         hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, true>), g, dim3(64), 0, s, A, keys);
@@ -856,6 +937,29 @@ hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s) {
     if (mode == ARA_SUM_KAHAN32) return f64out ? su_dispatch2<ARA_SUM_KAHAN32, true>(p, s)
                                                : su_dispatch2<ARA_SUM_KAHAN32, false>(p, s);
     return f64out ? su_dispatch2<ARA_SUM_F64, true>(p, s) : su_dispatch2<ARA_SUM_F64, false>(p, s);
+}
+
+template <int MODE, bool F64OUT>
+static void batch_dispatch(const BatchArgs &B, int grid, int redo_grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B.counter, B.redo_count);
+    hipLaunchKernelGGL((k_ara_batch<MODE, F64OUT>), dim3(grid), dim3(64), 0, s, B);
+    hipLaunchKernelGGL((k_ara_batch_redo<MODE, F64OUT>), dim3(redo_grid), dim3(64), 0, s, B);
+}
+
+hipError_t launch_batch(const BatchArgs &B, int mode, bool f64out, int grid, int redo_grid,
+                        hipStream_t s) {
+    if (B.trial_count <= 0 || B.n_pf <= 0) return hipSuccess;
+    if (mode == ARA_SUM_NAIVE32) {
+        if (f64out) batch_dispatch<ARA_SUM_NAIVE32, true>(B, grid, redo_grid, s);
+        else batch_dispatch<ARA_SUM_NAIVE32, false>(B, grid, redo_grid, s);
+    } else if (mode == ARA_SUM_KAHAN32) {
+        if (f64out) batch_dispatch<ARA_SUM_KAHAN32, true>(B, grid, redo_grid, s);
+        else batch_dispatch<ARA_SUM_KAHAN32, false>(B, grid, redo_grid, s);
+    } else {
+        if (f64out) batch_dispatch<ARA_SUM_F64, true>(B, grid, redo_grid, s);
+        else batch_dispatch<ARA_SUM_F64, false>(B, grid, redo_grid, s);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out,
