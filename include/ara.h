@@ -222,6 +222,69 @@ ara_status ara_batch_graph_create(ara_context *ctx, const ara_yet *yet, int32_t 
 ara_status ara_graph_launch(ara_context *ctx, ara_graph *graph, void *stream);
 ara_status ara_graph_destroy(ara_context *ctx, ara_graph *graph);
 
+/* ---- serving ------------------------------------------------------------
+ * A request loop over a YET resident in HBM.  Portfolio-pricing requests
+ * (a portfolio description, a trial range, return periods) are queued by
+ * ara_server_submit from any host thread; a worker thread admits them in
+ * arrival order as far as their HBM footprint (portfolio workspace, YLT
+ * outputs, metric scratch) fits the caller's device pool, launches every
+ * admitted group as one batched launch with a trial range per request on one
+ * of max_inflight streams -- so groups admitted while others run overlap on
+ * the device -- and on completion takes PML / TVaR and records latencies.
+ * A request's result does not depend on what it was batched with: it is bit
+ * for bit the result of the same request submitted alone (the draws are keyed
+ * by trial, occurrence and ELT id, and each trial is summed by one wavefront).
+ * Secondary-uncertainty portfolios also equal ara_run bit for bit; primary-
+ * uncertainty ones take the batched per-occurrence path and agree with
+ * ara_run to FP32 rounding.  The server creates one context per stream on
+ * hip_device; the YET arrays and the pool are borrowed and must outlive the
+ * server.  A request that fails validation fails alone (its result carries
+ * the status; ara_server_last_error gives the message of the last failure). */
+typedef struct ara_server ara_server;
+
+typedef struct {
+    int32_t max_inflight;       /* request groups in flight (streams); <= 0: 4 */
+    int32_t max_batch;          /* requests per batched launch; <= 0: 16 */
+    int32_t sum_mode;           /* ARA_SUM_* */
+    int32_t reserved;
+    void *d_pool;               /* device memory the server sub-allocates requests from */
+    size_t pool_bytes;
+} ara_server_config;
+
+#define ARA_SERVER_MAX_RP 16
+
+typedef struct {
+    uint64_t request_id;
+    ara_status status;
+    int32_t n_rp;
+    double pml[ARA_SERVER_MAX_RP];
+    double tvar[ARA_SERVER_MAX_RP];
+    double queue_s;             /* submission -> launch of its group */
+    double latency_s;           /* submission -> PML / TVaR ready on the host */
+    const float *ylt;           /* host copy of the portfolio YLT if requested, else NULL;
+                                   valid until ara_server_release(request_id) */
+    int64_t ylt_count;
+} ara_server_result;
+
+ara_status ara_server_create(int hip_device, int64_t n_trials, int32_t n_catalogue,
+                             const int64_t *d_trial_offsets, const int32_t *d_event_ids,
+                             const ara_server_config *cfg, ara_server **out);
+/* Copies the description; fails with ARA_E_WORKSPACE_TOO_SMALL when the
+ * request alone can never fit the pool. */
+ara_status ara_server_submit(ara_server *srv, const ara_portfolio_desc *desc, int64_t trial_begin,
+                             int64_t trial_count, const double *return_periods, int32_t n_rp,
+                             int32_t want_ylt, uint64_t *request_id);
+/* Up to max_results finished requests (waiting up to wait_s seconds for the
+ * first one); *n_out receives the count. */
+ara_status ara_server_poll(ara_server *srv, ara_server_result *out, int32_t max_results,
+                           double wait_s, int32_t *n_out);
+ara_status ara_server_release(ara_server *srv, uint64_t request_id);
+/* Stops after the queued and running requests finish, joins the worker. */
+ara_status ara_server_destroy(ara_server *srv);
+/* Message of the most recent failed request; the pointer stays valid in the
+ * calling thread until its next call. */
+const char *ara_server_last_error(ara_server *srv);
+
 /* ---- risk metrics (section 2.3) -------------------------------------------
  * PML and TVaR of the n losses in d_ylt (ARA_F32 or ARA_F64, all >= 0) for
  * n_rp return periods; results to host arrays pml_out / tvar_out.  The k-th

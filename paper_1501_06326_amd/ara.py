@@ -40,7 +40,10 @@ EXPORTS = ["ara_create", "ara_destroy", "ara_status_string", "ara_last_error", "
            "ara_pml_tvar_scratch_size", "ara_pml_tvar", "ara_debug_philox",
            "ara_debug_beta_quantile", "ara_batch_scratch_size", "ara_run_batch",
            "ara_batch_autotune", "ara_batch_graph_create", "ara_graph_launch",
-           "ara_graph_destroy"]
+           "ara_graph_destroy", "ara_server_create", "ara_server_submit", "ara_server_poll",
+           "ara_server_release", "ara_server_destroy", "ara_server_last_error"]
+
+SERVER_MAX_RP = 16
 
 
 class AraError(RuntimeError):
@@ -70,6 +73,18 @@ class ara_portfolio_desc(C.Structure):
 
 class ara_batch_config(C.Structure):
     _fields_ = [("trial_tile", C.c_int32), ("waves_per_cu", C.c_int32)]
+
+
+class ara_server_config(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("max_batch", C.c_int32), ("sum_mode", C.c_int32),
+                ("reserved", C.c_int32), ("d_pool", C.c_void_p), ("pool_bytes", C.c_size_t)]
+
+
+class ara_server_result(C.Structure):
+    _fields_ = [("request_id", C.c_uint64), ("status", C.c_int32), ("n_rp", C.c_int32),
+                ("pml", C.c_double * 16), ("tvar", C.c_double * 16), ("queue_s", C.c_double),
+                ("latency_s", C.c_double), ("ylt", C.POINTER(C.c_float)),
+                ("ylt_count", C.c_int64)]
 
 
 class ara_run_opts(C.Structure):
@@ -124,6 +139,16 @@ def lib():
                                              C.POINTER(p)]
         L.ara_graph_launch.argtypes = [p, p, p]
         L.ara_graph_destroy.argtypes = [p, p]
+        L.ara_server_create.argtypes = [C.c_int, i64, i32, p, p, C.POINTER(ara_server_config),
+                                        C.POINTER(p)]
+        L.ara_server_submit.argtypes = [p, C.POINTER(ara_portfolio_desc), i64, i64, p, i32, i32,
+                                        C.POINTER(C.c_uint64)]
+        L.ara_server_poll.argtypes = [p, C.POINTER(ara_server_result), i32, C.c_double,
+                                      C.POINTER(i32)]
+        L.ara_server_release.argtypes = [p, C.c_uint64]
+        L.ara_server_destroy.argtypes = [p]
+        L.ara_server_last_error.argtypes = [p]
+        L.ara_server_last_error.restype = C.c_char_p
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is C.c_int:       # default
@@ -292,6 +317,50 @@ def ara_graph_launch(ctx, graph, stream: Optional[int]) -> None:
 
 def ara_graph_destroy(ctx, graph) -> None:
     _check(ctx, lib().ara_graph_destroy(ctx, graph), "ara_graph_destroy")
+
+
+def ara_server_create(device: int, n_trials: int, n_catalogue: int, d_offsets: int,
+                      d_event_ids: int, cfg: "ara_server_config"):
+    h = C.c_void_p()
+    rc = lib().ara_server_create(int(device), int(n_trials), int(n_catalogue), d_offsets,
+                                 d_event_ids, C.byref(cfg), C.byref(h))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_server_create: " + ara_status_string(rc))
+    return h
+
+
+def ara_server_submit(srv, desc: "ara_portfolio_desc", trial_begin: int, trial_count: int,
+                      return_periods, want_ylt: bool) -> int:
+    rp = np.ascontiguousarray(return_periods, np.float64)
+    rid = C.c_uint64()
+    rc = lib().ara_server_submit(srv, C.byref(desc), int(trial_begin), int(trial_count),
+                                 rp.ctypes.data, rp.shape[0], 1 if want_ylt else 0, C.byref(rid))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_server_submit: " + ara_status_string(rc))
+    return int(rid.value)
+
+
+def ara_server_poll(srv, max_results: int, wait_s: float):
+    out = (ara_server_result * max_results)()
+    n = C.c_int32()
+    rc = lib().ara_server_poll(srv, out, int(max_results), float(wait_s), C.byref(n))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_server_poll")
+    return [out[i] for i in range(n.value)]
+
+
+def ara_server_release(srv, request_id: int) -> None:
+    rc = lib().ara_server_release(srv, int(request_id))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_server_release")
+
+
+def ara_server_destroy(srv) -> None:
+    lib().ara_server_destroy(srv)
+
+
+def ara_server_last_error(srv) -> str:
+    return lib().ara_server_last_error(srv).decode()
 
 
 def _ptr(t) -> Optional[int]:
@@ -563,3 +632,57 @@ def evaluations(yet, pf, trial_begin: int = 0, trial_count: Optional[int] = None
 
 
 __all__ = [n for n in EXPORTS] + ["Ara", "AraError", "lib", "evaluations", "SUM_MODES"]
+
+
+class Server:
+    """Serving loop (ara_server_*): a YET resident on the device, requests
+    admitted by HBM footprint from a pool tensor, continuous batching on
+    max_inflight streams.  Requests are workloads.Portfolio objects."""
+
+    def __init__(self, yet, device: int = 0, pool_bytes: int = 4 << 30, max_inflight: int = 4,
+                 max_batch: int = 16, sum_mode: str = "naive32", device_arrays=None):
+        import torch
+        self.torch = torch
+        dev = torch.device("cuda", device)
+        if device_arrays is None:
+            self.off = torch.from_numpy(np.ascontiguousarray(yet.offsets, np.int64)).to(dev)
+            self.ev = torch.from_numpy(np.ascontiguousarray(yet.event_ids, np.int32)).to(dev)
+        else:
+            self.off, self.ev = device_arrays[0], device_arrays[1]
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        cfg = ara_server_config(max_inflight=int(max_inflight), max_batch=int(max_batch),
+                                sum_mode=SUM_MODES[sum_mode], reserved=0,
+                                d_pool=self.pool.data_ptr(), pool_bytes=int(pool_bytes))
+        self.h = ara_server_create(device, int(self.off.shape[0] - 1), int(yet.n_catalogue),
+                                   _ptr(self.off), _ptr(self.ev), cfg)
+
+    def submit(self, pf, trial_begin: int, trial_count: int, return_periods=(100.0, 250.0),
+               want_ylt: bool = False) -> int:
+        d = _Desc(pf)     # the server copies the description during the call
+        return ara_server_submit(self.h, d.desc, trial_begin, trial_count, return_periods,
+                                 want_ylt)
+
+    def poll(self, max_results: int = 64, wait_s: float = 0.0):
+        res = []
+        for r in ara_server_poll(self.h, max_results, wait_s):
+            item = {"id": int(r.request_id), "status": int(r.status),
+                    "pml": np.array(r.pml[:r.n_rp]), "tvar": np.array(r.tvar[:r.n_rp]),
+                    "queue_s": float(r.queue_s), "latency_s": float(r.latency_s), "ylt": None}
+            if r.ylt_count > 0 and bool(r.ylt):
+                item["ylt"] = np.ctypeslib.as_array(r.ylt, shape=(int(r.ylt_count),)).copy()
+            ara_server_release(self.h, r.request_id)
+            res.append(item)
+        return res
+
+    def close(self):
+        if self.h is not None:
+            ara_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+

@@ -610,10 +610,14 @@ struct BatchPlan {
     bool f64out;
 };
 
-ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portfolio *const *pfs,
-                      const ara_run_opts *opts, const ara_batch_config *cfg,
-                      void *const *ylt_l, void *const *ylt_p, void *scratch, size_t bytes,
-                      hipStream_t s, BatchPlan *plan) {
+// Validate a batch and upload its portfolio table.  ranges: per portfolio
+// (trial_begin, trial_count), or null for opts' common range (trial-major
+// work items).
+ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
+                             ara_portfolio *const *pfs, const ara_run_opts *opts,
+                             const ara_batch_config *cfg, void *const *ylt_l, void *const *ylt_p,
+                             const int64_t *ranges, void *scratch, size_t bytes, hipStream_t s,
+                             BatchPlan *plan) {
     if (!yet || !ctx->yets.count(const_cast<ara_yet *>(yet)) || n <= 0 || !pfs)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad YET or portfolio list");
     ara_run_opts o;
@@ -621,9 +625,6 @@ ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portf
     o.trial_count = -1;
     if (opts) o = *opts;
     if (o.trial_count < 0) o.trial_count = yet->n_trials - o.trial_begin;
-    if (o.trial_begin < 0 || o.trial_begin + o.trial_count > yet->n_trials ||
-        o.trial_count > 0x7fffffff)
-        return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: trial range outside the YET");
     if (o.sum_mode < ARA_SUM_NAIVE32 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
         o.ylt_dtype > ARA_F64)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad sum_mode or ylt_dtype");
@@ -634,11 +635,14 @@ ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portf
     if (cfg) c = *cfg;
     if (c.trial_tile < 1 || c.waves_per_cu < 1)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad batch configuration");
-    const size_t need = batch_need(n, o.trial_count);
-    if (!scratch || bytes < need)
-        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_run_batch: need %zu scratch bytes", need);
+    int64_t max_count = 0, items = 0;
     std::vector<BatchPf> h((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
+        const int64_t tb = ranges ? ranges[2 * i] : o.trial_begin;
+        const int64_t tc = ranges ? ranges[2 * i + 1] : o.trial_count;
+        if (tb < 0 || tc < 0 || tb + tc > yet->n_trials || tc > 0x7fffffff)
+            return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: trial range of portfolio %d outside "
+                                                "the YET", i);
         const ara_portfolio *p = pfs[i];
         if (!p || !ctx->pfs.count(const_cast<ara_portfolio *>(p)))
             return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: unknown portfolio %d", i);
@@ -659,19 +663,29 @@ ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portf
         b.k1 = (uint32_t)(p->seed >> 32);
         b.n_layers = p->n_layers;
         b.pad = 0;
+        b.trial_begin = tb;
+        b.trial_count = tc;
+        b.tile_base = items;
+        items += (tc + c.trial_tile - 1) / c.trial_tile;
+        if (tc > max_count) max_count = tc;
     }
+    const size_t need = batch_need(n, max_count);
+    if (!scratch || bytes < need)
+        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_run_batch: need %zu scratch bytes", need);
     char *sc = (char *)scratch;
     ARA_HIP(ctx, hipMemcpyAsync(sc + batch_pf_off(), h.data(), sizeof(BatchPf) * h.size(),
                                 hipMemcpyHostToDevice, s));
     BatchArgs &B = plan->B;
     B.off = yet->d_off;
     B.ev = yet->d_ev;
-    B.trial_begin = o.trial_begin;
-    B.trial_count = o.trial_count;
+    B.trial_begin = ranges ? 0 : o.trial_begin;
+    B.trial_count = ranges ? 0 : o.trial_count;
     B.pfs = (const BatchPf *)(sc + batch_pf_off());
     B.n_pf = n;
     B.tile = c.trial_tile;
     B.tail_band = o.tail_band;
+    B.trial_major = ranges ? 0 : 1;
+    B.n_items = ranges ? items : ((o.trial_count + c.trial_tile - 1) / c.trial_tile) * (int64_t)n;
     B.counter = (unsigned long long *)sc;
     B.redo_count = (uint32_t *)(sc + 8);
     B.redo = (unsigned long long *)(sc + batch_redo_off(n));
@@ -681,6 +695,14 @@ ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portf
     plan->mode = o.sum_mode;
     plan->f64out = o.ylt_dtype == ARA_F64;
     return ARA_OK;
+}
+
+ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portfolio *const *pfs,
+                      const ara_run_opts *opts, const ara_batch_config *cfg,
+                      void *const *ylt_l, void *const *ylt_p, void *scratch, size_t bytes,
+                      hipStream_t s, BatchPlan *plan) {
+    return prep_batch_ranges(ctx, yet, n, pfs, opts, cfg, ylt_l, ylt_p, nullptr, scratch, bytes, s,
+                             plan);
 }
 
 }  // namespace
@@ -839,3 +861,22 @@ ara_status ara_debug_beta_quantile(ara_context *ctx, int64_t n, const float *d_a
 }
 
 }  // extern "C"
+
+namespace ara {
+ara_status run_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
+                            ara_portfolio *const *pfs, const ara_run_opts *opts,
+                            const ara_batch_config *cfg, void *const *ylt_l, void *const *ylt_p,
+                            const int64_t *ranges, void *scratch, size_t bytes, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    BatchPlan plan;
+    ara_status st = prep_batch_ranges(ctx, yet, n, pfs, opts, cfg, ylt_l, ylt_p, ranges, scratch,
+                                      bytes, s, &plan);
+    if (st != ARA_OK) return st;
+    ARA_HIP(ctx, launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s));
+    return ARA_OK;
+}
+size_t batch_scratch_need(int32_t n, int64_t max_trials) { return batch_need(n, max_trials); }
+}  // namespace ara
+

@@ -109,3 +109,14 @@ struct ara_portfolio {
     size_t workspace_bytes;
     ara::LayerDev *h_layers;   // host copy
 };
+
+namespace ara {
+// Batched run with a trial range per portfolio (ranges[2i], ranges[2i+1]);
+// defined with the C-ABI, used by the serving loop.
+ara_status run_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
+                            ara_portfolio *const *pfs, const ara_run_opts *opts,
+                            const ara_batch_config *cfg, void *const *ylt_l, void *const *ylt_p,
+                            const int64_t *ranges, void *scratch, size_t bytes, void *stream);
+size_t batch_scratch_need(int32_t n, int64_t max_trials);
+}  // namespace ara
+

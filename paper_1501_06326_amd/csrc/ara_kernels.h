@@ -66,6 +66,8 @@ struct BatchPf {
     uint32_t k0, k1;           // Philox key (the portfolio's seed)
     int32_t n_layers;
     int32_t pad;
+    int64_t trial_begin, trial_count;   // the portfolio's trial range
+    int64_t tile_base;                  // its first work item (trial-major off)
 };
 
 struct BatchArgs {
@@ -76,6 +78,8 @@ struct BatchArgs {
     int32_t n_pf;
     int32_t tile;                       // trials per work item
     float tail_band;
+    int32_t trial_major;                // 1: one common range, items (tile, portfolio)
+    int64_t n_items;                    // work items
     unsigned long long *counter;        // work-item counter
     unsigned long long *redo;           // (portfolio << 32 | trial) handed to the FP64 pass
     uint32_t *redo_count;

@@ -700,8 +700,8 @@ __device__ __forceinline__ void batch_view(const BatchArgs &B, int p, SuArgs &A,
     const BatchPf &P = B.pfs[p];
     A.off = B.off;
     A.ev = B.ev;
-    A.trial_begin = B.trial_begin;
-    A.trial_count = B.trial_count;
+    A.trial_begin = P.trial_begin;
+    A.trial_count = P.trial_count;
     A.layers = P.layers;
     A.n_layers = P.n_layers;
     A.elts = P.elts;
@@ -728,8 +728,7 @@ __global__ __launch_bounds__(64) void k_ara_batch(BatchArgs B) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
     const int lane = threadIdx.x;
-    const int64_t n_tiles = (B.trial_count + B.tile - 1) / B.tile;
-    const unsigned long long n_items = (unsigned long long)n_tiles * (unsigned long long)B.n_pf;
+    const unsigned long long n_items = (unsigned long long)B.n_items;
     while (true) {
         unsigned long long item = 0;
         if (lane == 0) item = atomicAdd(B.counter, 1ull);
@@ -737,13 +736,26 @@ __global__ __launch_bounds__(64) void k_ara_batch(BatchArgs B) {
         const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(item >> 32));
         item = ((unsigned long long)hi << 32) | lo;
         if (item >= n_items) break;
-        const int64_t tile = (int64_t)(item / (unsigned long long)B.n_pf);
-        const int p = (int)(item % (unsigned long long)B.n_pf);
+        int64_t tile;
+        int p;
+        if (B.trial_major) {
+            tile = (int64_t)(item / (unsigned long long)B.n_pf);
+            p = (int)(item % (unsigned long long)B.n_pf);
+        } else {
+            // the portfolio whose block of work items holds this item
+            int lo_p = 0, hi_p = B.n_pf - 1;
+            while (lo_p < hi_p) {
+                const int mid = (lo_p + hi_p + 1) >> 1;
+                if ((unsigned long long)B.pfs[mid].tile_base <= item) lo_p = mid; else hi_p = mid - 1;
+            }
+            p = lo_p;
+            tile = (int64_t)item - B.pfs[p].tile_base;
+        }
         SuArgs A;
         PhiloxKeys keys;
         batch_view(B, p, A, keys);
         const int64_t t0 = tile * B.tile;
-        const int64_t t1 = (t0 + B.tile) < B.trial_count ? (t0 + B.tile) : B.trial_count;
+        const int64_t t1 = (t0 + B.tile) < A.trial_count ? (t0 + B.tile) : A.trial_count;
         for (int64_t t = t0; t < t1; ++t)
             if (su_trial<MODE, F64OUT, false, false>(A, keys, t, X, Q) && lane == 0)
                 B.redo[atomicAdd(B.redo_count, 1u)] = ((unsigned long long)p << 32) | (uint64_t)t;
@@ -948,7 +960,7 @@ static void batch_dispatch(const BatchArgs &B, int grid, int redo_grid, hipStrea
 
 hipError_t launch_batch(const BatchArgs &B, int mode, bool f64out, int grid, int redo_grid,
                         hipStream_t s) {
-    if (B.trial_count <= 0 || B.n_pf <= 0) return hipSuccess;
+    if (B.n_items <= 0 || B.n_pf <= 0) return hipSuccess;
     if (mode == ARA_SUM_NAIVE32) {
         if (f64out) batch_dispatch<ARA_SUM_NAIVE32, true>(B, grid, redo_grid, s);
         else batch_dispatch<ARA_SUM_NAIVE32, false>(B, grid, redo_grid, s);
