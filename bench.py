@@ -12,6 +12,15 @@ occurrence counts, zero losses included).  Also reported: the primary-
 uncertainty variant of the same workload against the HBM roofline, the
 dominant kernel against its roofline, and the FP64 oracle timed on a bounded
 sample of trials on the host cores.
+
+Two further modes print their own JSON line:
+  --mode batched  64 portfolios (1-16 layers, 2-48 ELTs per layer, 1,000-50,000
+                  rows per ELT) on the same YET: one persistent batched launch
+                  against 64 sequential ara_run calls.
+  --mode served   the serving loop under Poisson arrivals of requests (1-8
+                  layers, 2-32 ELTs per layer, trial ranges of 1e4-1e6 trials):
+                  p50 / p99 latency and throughput at several offered loads,
+                  against a one-at-a-time server with the measured service times.
 """
 import argparse
 import json
@@ -51,11 +60,23 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a known-size kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--mode", choices=["step", "batched", "served"], default="step")
+    ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
+    ap.add_argument("--graph", action="store_true", help="batched mode: also time a graph replay")
+    ap.add_argument("--requests", type=int, default=1000, help="served mode: requests per load")
+    ap.add_argument("--loads", default="0.5,0.8,0.95,1.5",
+                    help="served mode: offered loads as fractions of one-at-a-time capacity")
+    ap.add_argument("--max-inflight", type=int, default=2, help="served mode: streams")
+    ap.add_argument("--max-batch", type=int, default=4, help="served mode: requests per launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by trial range, see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batched":
+        return bench_batched(args)
+    if args.mode == "served":
+        return bench_served(args)
 
     import torch
     from paper_1501_06326_amd import Ara, evaluations
@@ -198,6 +219,221 @@ def main():
 
     print(json.dumps(result), flush=True)
     ara.close()
+
+
+def _full_yet(n_trials):
+    from workloads import SEED_YET_FULL, make_yet
+    t0 = time.time()
+    yet = make_yet(n_trials, 1000.0, 100_000, SEED_YET_FULL, with_times=False)
+    log(f"generated YET: {n_trials} trials, {yet.n_occ} occurrences in {time.time() - t0:.1f}s")
+    return yet
+
+
+def bench_batched(args):
+    """64 portfolios on one YET: one batched launch vs sequential ara_run."""
+    import torch
+    from paper_1501_06326_amd import Ara, evaluations
+    from workloads import batched_portfolios
+
+    yet = _full_yet(args.trials)
+    n = yet.n_trials
+    t0 = time.time()
+    pfs = batched_portfolios(args.portfolios)
+    log(f"generated {len(pfs)} portfolios, {sum(p.n_elts for p in pfs)} ELTs "
+        f"in {time.time() - t0:.1f}s")
+    evals = sum(evaluations(yet, p) for p in pfs)
+    ara = Ara(0)
+    dev = ara.device
+    off = torch.from_numpy(yet.offsets).to(dev)
+    ev = torch.from_numpy(yet.event_ids).to(dev)
+    y = ara.load_yet(yet, device_arrays=(off, ev, None))
+    dps = []
+    for k, pf in enumerate(pfs):
+        dps.append(ara.load_portfolio(pf, yet.n_catalogue))
+        if k % 16 == 15:
+            log(f"loaded {k + 1} portfolios")
+    ws = sum(d.workspace.numel() for d in dps)
+    outs = [{"ylt": torch.empty((d.n_layers, n), dtype=torch.float32, device=dev),
+             "ylt_pf": torch.empty(n, dtype=torch.float32, device=dev)} for d in dps]
+    seq = [{"ylt": torch.empty_like(o["ylt"]), "ylt_pf": torch.empty_like(o["ylt_pf"])}
+           for o in outs]
+    scratch = torch.empty(ara.run_scratch_size(n), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    sub = min(n, 4_000)
+    cfg, tune_ms = ara.batch_autotune(y, dps, trial_count=sub)
+    log(f"autotuned (trial_tile, waves_per_cu) = {cfg} on {sub} trials ({tune_ms:.2f} ms)")
+    # warmup on a prefix of the trials
+    ara.run_batch(y, dps, trial_count=sub, cfg=cfg)
+    for d in dps:
+        ara.run(y, d, trial_count=sub, scratch=scratch)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record(stream)
+    for d, o in zip(dps, seq):
+        ara.run(y, d, out_layers=o["ylt"], out_pf=o["ylt_pf"], scratch=scratch, sync=False)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    ara.sync_status()
+    seq_ms = e[0].elapsed_time(e[1])
+    log(f"sequential: {seq_ms:.1f} ms")
+    e[2].record(stream)
+    ara.run_batch(y, dps, cfg=cfg, outs=outs, sync=False)
+    e[3].record(stream)
+    torch.cuda.synchronize()
+    ara.sync_status()
+    bat_ms = e[2].elapsed_time(e[3])
+    log(f"batched: {bat_ms:.1f} ms")
+    identical = all(torch.equal(a["ylt"], b["ylt"]) and torch.equal(a["ylt_pf"], b["ylt_pf"])
+                    for a, b in zip(outs, seq))
+    result = {
+        "metric": "batched trial*event*ELT evaluations/s (64 portfolios on the 1M-trial YET)",
+        "value": evals / (bat_ms / 1e3), "unit": "evaluations/s", "n_gpus": 1,
+        "ms_per_step": bat_ms, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic (seeded numpy generator; lognormal ELT means)",
+        "config": {"workload": f"ara_batched_{len(pfs)}_portfolios_{n}_trials",
+                   "portfolios": len(pfs), "layers": sum(len(p.layers) for p in pfs),
+                   "elts": sum(p.n_elts for p in pfs), "trials": n, "occurrences": yet.n_occ,
+                   "evaluations_per_step": evals, "workspace_bytes": ws,
+                   "batch_config": {"trial_tile": cfg[0], "waves_per_cu": cfg[1],
+                                    "order": ["portfolio-major", "trial-major"][cfg[2]]}},
+        "sequential": {"ms": seq_ms, "evaluations_per_s": evals / (seq_ms / 1e3)},
+        "speedup_vs_sequential": seq_ms / bat_ms,
+        "batched_equals_sequential": identical,
+    }
+    if args.graph:
+        g, gouts, gsc = ara.batch_graph(y, dps, cfg=cfg)
+        ara.graph_launch(g)
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        ara.graph_launch(g)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        result["graph_ms"] = e[0].elapsed_time(e[1])
+        result["graph_equals_eager"] = all(torch.equal(a["ylt_pf"], b["ylt_pf"])
+                                           for a, b in zip(gouts, outs))
+        ara.graph_destroy(g)
+    print(json.dumps(result), flush=True)
+    ara.close()
+
+
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def bench_served(args):
+    """Serving loop under Poisson arrivals against a one-at-a-time server."""
+    import threading
+
+    import torch
+    from paper_1501_06326_amd import Ara, Server, evaluations
+    from workloads import poisson_arrivals, served_requests
+
+    yet = _full_yet(args.trials)
+    t0 = time.time()
+    reqs = served_requests(args.requests, yet.n_trials)
+    log(f"generated {len(reqs)} requests in {time.time() - t0:.1f}s")
+    req_evals = [evaluations(yet, r.portfolio, r.trial_begin, r.trial_count) for r in reqs]
+    rps = [100.0, 250.0]
+    ara = Ara(0)
+    dev = ara.device
+    off = torch.from_numpy(yet.offsets).to(dev)
+    ev = torch.from_numpy(yet.event_ids).to(dev)
+    y = ara.load_yet(yet, device_arrays=(off, ev, None))
+
+    # one-at-a-time: load, run, PML / TVaR, free -- per request, synchronously
+    for r in reqs[:4]:
+        d = ara.load_portfolio(r.portfolio, yet.n_catalogue)
+        ara.pml_tvar(ara.run(y, d, r.trial_begin, r.trial_count)["ylt_pf"], rps)
+        ara.free_portfolio(d)
+    svc = []
+    for i, r in enumerate(reqs):
+        ts = time.perf_counter()
+        d = ara.load_portfolio(r.portfolio, yet.n_catalogue)
+        ara.pml_tvar(ara.run(y, d, r.trial_begin, r.trial_count)["ylt_pf"], rps)
+        ara.free_portfolio(d)
+        svc.append(time.perf_counter() - ts)
+        if i % 200 == 199:
+            log(f"one-at-a-time: {i + 1} requests, mean service {np.mean(svc) * 1e3:.1f} ms")
+    svc = np.asarray(svc)
+    capacity = len(reqs) / svc.sum()
+    total_evals = float(sum(req_evals))
+    log(f"one-at-a-time capacity {capacity:.2f} req/s, "
+        f"{total_evals / svc.sum():.3g} evaluations/s")
+    torch.cuda.empty_cache()
+
+    points = []
+    for f in [float(x) for x in args.loads.split(",")]:
+        rate = f * capacity
+        arr = poisson_arrivals(len(reqs), rate, seed=6 + int(f * 1000))
+        # one-at-a-time FIFO server with the measured service times
+        fin = 0.0
+        lat1 = []
+        for a, s_i in zip(arr, svc):
+            fin = max(a, fin) + s_i
+            lat1.append(fin - a)
+        with Server(yet, device_arrays=(off, ev), pool_bytes=32 << 30,
+                    max_inflight=args.max_inflight, max_batch=args.max_batch) as srv:
+            ids = {}
+            start = time.perf_counter() + 0.05
+            lock = threading.Lock()
+
+            def submitter():
+                for i, r in enumerate(reqs):
+                    dt = start + arr[i] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    rid = srv.submit(r.portfolio, r.trial_begin, r.trial_count, rps)
+                    with lock:
+                        ids[rid] = i
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            lat, done_t, n_err = [], [], 0
+            while len(lat) < len(reqs):
+                for res in srv.poll(64, wait_s=0.02):
+                    now = time.perf_counter()
+                    with lock:
+                        i = ids.get(res["id"])
+                    while i is None:           # result before the submitter recorded the id
+                        time.sleep(1e-4)
+                        with lock:
+                            i = ids.get(res["id"])
+                    n_err += res["status"] != 0
+                    lat.append(now - (start + arr[i]))
+                    done_t.append(now - start)
+                    if len(lat) % 250 == 0:
+                        log(f"load {f}: {len(lat)} done")
+            th.join()
+        span = max(done_t) - arr[0]
+        pt = {"offered_load": f, "rate_req_s": rate, "p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99),
+              "mean_s": float(np.mean(lat)), "achieved_req_s": len(reqs) / span,
+              "evaluations_per_s": total_evals / span, "errors": int(n_err),
+              "one_at_a_time": {"p50_s": _pct(lat1, 50), "p99_s": _pct(lat1, 99),
+                                "mean_s": float(np.mean(lat1))}}
+        log(f"load {f}: p50 {pt['p50_s'] * 1e3:.1f} ms p99 {pt['p99_s'] * 1e3:.1f} ms "
+            f"(one-at-a-time {pt['one_at_a_time']['p50_s'] * 1e3:.1f} / "
+            f"{pt['one_at_a_time']['p99_s'] * 1e3:.1f} ms), {pt['evaluations_per_s']:.3g} evals/s")
+        points.append(pt)
+    result = {
+        "metric": "served latency p50/p99 (s) and evaluations/s under Poisson arrivals",
+        "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+        "data": "synthetic (seeded numpy generator; lognormal ELT means)",
+        "config": {"workload": f"ara_served_{n_trials_label(yet)}_yet",
+                   "requests_per_load": len(reqs), "distinct_portfolios": 32,
+                   "trials": yet.n_trials, "max_inflight": args.max_inflight,
+                   "max_batch": args.max_batch, "return_periods": rps},
+        "one_at_a_time": {"capacity_req_s": capacity,
+                          "evaluations_per_s": total_evals / svc.sum(),
+                          "mean_service_s": float(svc.mean()),
+                          "p50_service_s": _pct(svc, 50), "p99_service_s": _pct(svc, 99)},
+        "points": points,
+    }
+    print(json.dumps(result), flush=True)
+    ara.close()
+
+
+def n_trials_label(yet):
+    return f"{yet.n_trials // 1000}k" if yet.n_trials < 1_000_000 else f"{yet.n_trials // 1_000_000}M"
 
 
 if __name__ == "__main__":

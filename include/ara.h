@@ -180,18 +180,28 @@ ara_status ara_sync_status(ara_context *ctx, void *stream);
 
 /* ---- batched portfolios --------------------------------------------------
  * Several portfolios (Algorithm 1's outer portfolio / program loops) over one
- * YET in one persistent launch: work items are (tile of trial_tile trials,
- * portfolio), taken trial-major from an atomic counter so that the
- * portfolios of one tile run close together and reuse its event ids from
- * cache.  Results are bit-identical to running each portfolio alone with
- * ara_run.  d_ylt_layers / d_ylt_portfolio are host arrays of n_portfolios
- * device pointers (entries may be NULL), laid out as for ara_run over
- * opts->trial_count trials.  opts->d_hits / d_hit_chk must be NULL; its
- * d_scratch is not used (the batch scratch is the explicit argument,
- * ara_batch_scratch_size bytes).  cfg = NULL: trial_tile 4, 16 waves per CU. */
+ * YET in one persistent launch.  Work items are (tile of trial_tile trials,
+ * portfolio), handed out from an atomic counter in one of two orders:
+ * portfolio-major (each portfolio's tiles in turn: its ELT tables stay in the
+ * caches, the better order when the draws dominate) or trial-major (the
+ * portfolios of one tile together: the tile's event ids are read once for all
+ * of them, the better order for primary-uncertainty batches, which are bound
+ * by memory traffic).  Results are bit-identical to running each secondary-
+ * uncertainty portfolio alone with ara_run; primary-uncertainty portfolios
+ * take the per-occurrence path, whose trial sum is ordered differently from
+ * ara_run's, and agree with it to FP32 rounding.  d_ylt_layers /
+ * d_ylt_portfolio are host arrays of n_portfolios device pointers (entries
+ * may be NULL), laid out as for ara_run over opts->trial_count trials.
+ * opts->d_hits / d_hit_chk must be NULL; its d_scratch is not used (the batch
+ * scratch is the explicit argument, ara_batch_scratch_size bytes).
+ * cfg = NULL: trial_tile 4, 16 waves per CU, portfolio-major unless every
+ * portfolio is primary-uncertainty. */
+#define ARA_BATCH_PORTFOLIO_MAJOR 0
+#define ARA_BATCH_TRIAL_MAJOR 1
 typedef struct {
     int32_t trial_tile;         /* trials per work item (>= 1) */
     int32_t waves_per_cu;       /* resident wavefronts per compute unit (>= 1) */
+    int32_t order;              /* ARA_BATCH_PORTFOLIO_MAJOR or ARA_BATCH_TRIAL_MAJOR */
 } ara_batch_config;
 
 ara_status ara_batch_scratch_size(int32_t n_portfolios, int64_t trial_count, size_t *bytes);
@@ -201,9 +211,10 @@ ara_status ara_run_batch(ara_context *ctx, const ara_yet *yet, int32_t n_portfol
                          void *const *d_ylt_portfolio, void *d_scratch, size_t scratch_bytes,
                          void *stream);
 
-/* Autotuner: times ara_run_batch over opts' trial range for trial tiles
- * {1, 2, 4, 8} x {8, 12, 16, 20} waves per CU (HIP events, after one warmup)
- * and returns the fastest configuration and its time.  Synchronises. */
+/* Autotuner: times ara_run_batch over opts' trial range (HIP events, after
+ * one warmup launch) for trial tiles {1, 2, 4} x {12, 16, 20} waves per CU x
+ * both orders and returns the fastest configuration and its time.  A range
+ * of a few thousand trials keeps it to seconds.  Synchronises. */
 ara_status ara_batch_autotune(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
                               ara_portfolio *const *pfs, const ara_run_opts *opts,
                               void *const *d_ylt_layers, void *const *d_ylt_portfolio,

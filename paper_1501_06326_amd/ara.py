@@ -71,8 +71,19 @@ class ara_portfolio_desc(C.Structure):
                 ("seed", C.c_uint64), ("su_enabled", C.c_int32)]
 
 
+ARA_BATCH_PORTFOLIO_MAJOR, ARA_BATCH_TRIAL_MAJOR = 0, 1
+
+
 class ara_batch_config(C.Structure):
-    _fields_ = [("trial_tile", C.c_int32), ("waves_per_cu", C.c_int32)]
+    _fields_ = [("trial_tile", C.c_int32), ("waves_per_cu", C.c_int32), ("order", C.c_int32)]
+
+
+def _batch_cfg(cfg):
+    """(trial_tile, waves_per_cu[, order]) -> ara_batch_config; None -> None."""
+    if cfg is None:
+        return None
+    t = tuple(cfg) + ((ARA_BATCH_PORTFOLIO_MAJOR,) if len(cfg) == 2 else ())
+    return ara_batch_config(*t)
 
 
 class ara_server_config(C.Structure):
@@ -490,6 +501,10 @@ class Ara:
     def free_portfolio(self, p: DevicePortfolio):
         ara_free_portfolio(self.ctx, p.handle)
 
+    def sync_status(self, stream=None):
+        """Wait for the stream and raise on a device-side error of its runs."""
+        ara_sync_status(self.ctx, _stream_handle(stream))
+
     # -- analysis ---------------------------------------------------------------
     def run(self, y: DeviceYET, p: DevicePortfolio, trial_begin: int = 0,
             trial_count: Optional[int] = None, sum_mode: str = "naive32",
@@ -566,7 +581,7 @@ class Ara:
                                         tail_band, outs)
         if scratch is not None:
             sc = scratch
-        c = None if cfg is None else ara_batch_config(*cfg)
+        c = _batch_cfg(cfg)
         s = _stream_handle(stream)
         ara_run_batch(self.ctx, y.handle, [p.handle.value for p in pfs], o, c,
                       [_ptr(r["ylt"]) for r in outs], [_ptr(r["ylt_pf"]) for r in outs],
@@ -582,7 +597,7 @@ class Ara:
                                       [_ptr(r["ylt"]) for r in outs],
                                       [_ptr(r["ylt_pf"]) for r in outs], _ptr(sc), sc.numel(),
                                       _stream_handle(stream))
-        return (best.trial_tile, best.waves_per_cu), ms
+        return (best.trial_tile, best.waves_per_cu, best.order), ms
 
     def batch_graph(self, y, pfs, trial_begin=0, trial_count=None, sum_mode="naive32",
                     ylt_dtype="f32", cfg=None):
@@ -590,7 +605,7 @@ class Ara:
         scratch); keep outs and scratch alive while the graph exists."""
         o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, sum_mode, ylt_dtype,
                                         0.0, None)
-        c = None if cfg is None else ara_batch_config(*cfg)
+        c = _batch_cfg(cfg)
         g = ara_batch_graph_create(self.ctx, y.handle, [p.handle.value for p in pfs], o, c,
                                    [_ptr(r["ylt"]) for r in outs],
                                    [_ptr(r["ylt_pf"]) for r in outs], _ptr(sc), sc.numel())
@@ -631,7 +646,8 @@ def evaluations(yet, pf, trial_begin: int = 0, trial_count: Optional[int] = None
     return occ * sum(len(l.elts) for l in pf.layers)
 
 
-__all__ = [n for n in EXPORTS] + ["Ara", "AraError", "lib", "evaluations", "SUM_MODES"]
+__all__ = [n for n in EXPORTS] + ["Ara", "AraError", "Server", "lib", "evaluations",
+                                  "SUM_MODES"]
 
 
 class Server:
@@ -639,8 +655,8 @@ class Server:
     admitted by HBM footprint from a pool tensor, continuous batching on
     max_inflight streams.  Requests are workloads.Portfolio objects."""
 
-    def __init__(self, yet, device: int = 0, pool_bytes: int = 4 << 30, max_inflight: int = 4,
-                 max_batch: int = 16, sum_mode: str = "naive32", device_arrays=None):
+    def __init__(self, yet, device: int = 0, pool_bytes: int = 4 << 30, max_inflight: int = 2,
+                 max_batch: int = 4, sum_mode: str = "naive32", device_arrays=None):
         import torch
         self.torch = torch
         dev = torch.device("cuda", device)

@@ -600,8 +600,9 @@ namespace {
 
 size_t batch_pf_off() { return 256; }
 size_t batch_redo_off(int32_t n) { return align256(batch_pf_off() + sizeof(BatchPf) * (size_t)n); }
-size_t batch_need(int32_t n, int64_t trials) {
-    return batch_redo_off(n) + sizeof(unsigned long long) * (size_t)n * (size_t)(trials > 0 ? trials : 1);
+// the redo list holds at most one entry per (portfolio, trial) of the batch
+size_t batch_need(int32_t n, int64_t total_trials) {
+    return batch_redo_off(n) + sizeof(unsigned long long) * (size_t)(total_trials > 0 ? total_trials : 1);
 }
 
 struct BatchPlan {
@@ -611,13 +612,13 @@ struct BatchPlan {
 };
 
 // Validate a batch and upload its portfolio table.  ranges: per portfolio
-// (trial_begin, trial_count), or null for opts' common range (trial-major
-// work items).
+// (trial_begin, trial_count), or null for opts' common range.  Trial-major
+// order needs the common range.
 ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
                              ara_portfolio *const *pfs, const ara_run_opts *opts,
                              const ara_batch_config *cfg, void *const *ylt_l, void *const *ylt_p,
                              const int64_t *ranges, void *scratch, size_t bytes, hipStream_t s,
-                             BatchPlan *plan) {
+                             Status *status, BatchPlan *plan) {
     if (!yet || !ctx->yets.count(const_cast<ara_yet *>(yet)) || n <= 0 || !pfs)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad YET or portfolio list");
     ara_run_opts o;
@@ -631,11 +632,19 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     if (o.d_hits || o.d_hit_chk)
         return fail(ctx, ARA_E_UNSUPPORTED, "ara_run_batch: hit diagnostics are per-portfolio only");
     if (!(o.tail_band > 0.0f)) o.tail_band = kDefaultTailBand;
-    ara_batch_config c = {4, 16};
-    if (cfg) c = *cfg;
-    if (c.trial_tile < 1 || c.waves_per_cu < 1)
+    ara_batch_config c = {4, 16, ARA_BATCH_TRIAL_MAJOR};
+    if (cfg) {
+        c = *cfg;
+    } else {
+        for (int32_t i = 0; i < n; ++i)
+            if (pfs && pfs[i] && pfs[i]->su_enabled) c.order = ARA_BATCH_PORTFOLIO_MAJOR;
+    }
+    if (c.trial_tile < 1 || c.waves_per_cu < 1 ||
+        (c.order != ARA_BATCH_PORTFOLIO_MAJOR && c.order != ARA_BATCH_TRIAL_MAJOR))
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad batch configuration");
-    int64_t max_count = 0, items = 0;
+    if (ranges && c.order == ARA_BATCH_TRIAL_MAJOR)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: trial-major order needs one trial range");
+    int64_t total = 0, items = 0;
     std::vector<BatchPf> h((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
         const int64_t tb = ranges ? ranges[2 * i] : o.trial_begin;
@@ -667,9 +676,9 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
         b.trial_count = tc;
         b.tile_base = items;
         items += (tc + c.trial_tile - 1) / c.trial_tile;
-        if (tc > max_count) max_count = tc;
+        total += tc;
     }
-    const size_t need = batch_need(n, max_count);
+    const size_t need = batch_need(n, total);
     if (!scratch || bytes < need)
         return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_run_batch: need %zu scratch bytes", need);
     char *sc = (char *)scratch;
@@ -678,18 +687,19 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     BatchArgs &B = plan->B;
     B.off = yet->d_off;
     B.ev = yet->d_ev;
-    B.trial_begin = ranges ? 0 : o.trial_begin;
-    B.trial_count = ranges ? 0 : o.trial_count;
+    const bool trial_major = c.order == ARA_BATCH_TRIAL_MAJOR;
+    B.trial_begin = trial_major ? o.trial_begin : 0;
+    B.trial_count = trial_major ? o.trial_count : 0;
     B.pfs = (const BatchPf *)(sc + batch_pf_off());
     B.n_pf = n;
     B.tile = c.trial_tile;
     B.tail_band = o.tail_band;
-    B.trial_major = ranges ? 0 : 1;
-    B.n_items = ranges ? items : ((o.trial_count + c.trial_tile - 1) / c.trial_tile) * (int64_t)n;
+    B.trial_major = trial_major ? 1 : 0;
+    B.n_items = trial_major ? ((o.trial_count + c.trial_tile - 1) / c.trial_tile) * (int64_t)n : items;
     B.counter = (unsigned long long *)sc;
     B.redo_count = (uint32_t *)(sc + 8);
     B.redo = (unsigned long long *)(sc + batch_redo_off(n));
-    B.status = ctx->d_status;
+    B.status = status ? status : ctx->d_status;
     plan->grid = ctx->n_cu * c.waves_per_cu;
     plan->redo_grid = ctx->n_cu * 4;
     plan->mode = o.sum_mode;
@@ -702,14 +712,14 @@ ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portf
                       void *const *ylt_l, void *const *ylt_p, void *scratch, size_t bytes,
                       hipStream_t s, BatchPlan *plan) {
     return prep_batch_ranges(ctx, yet, n, pfs, opts, cfg, ylt_l, ylt_p, nullptr, scratch, bytes, s,
-                             plan);
+                             nullptr, plan);
 }
 
 }  // namespace
 
 ara_status ara_batch_scratch_size(int32_t n_portfolios, int64_t trial_count, size_t *bytes) {
     if (!bytes || n_portfolios <= 0 || trial_count < 0) return ARA_E_INVALID_ARG;
-    *bytes = batch_need(n_portfolios, trial_count);
+    *bytes = batch_need(n_portfolios, (int64_t)n_portfolios * trial_count);
     return ARA_OK;
 }
 
@@ -741,35 +751,42 @@ ara_status ara_batch_autotune(ara_context *ctx, const ara_yet *yet, int32_t n_po
     hipEvent_t e0, e1;
     ARA_HIP(ctx, hipEventCreate(&e0));
     ARA_HIP(ctx, hipEventCreate(&e1));
-    const int tiles[] = {1, 2, 4, 8};
-    const int waves[] = {8, 12, 16, 20};
+    const int tiles[] = {1, 2, 4};
+    const int waves[] = {12, 16, 20};
+    const int orders[] = {ARA_BATCH_PORTFOLIO_MAJOR, ARA_BATCH_TRIAL_MAJOR};
     double bms = 1e300;
-    ara_batch_config bc = {4, 16};
+    ara_batch_config bc = {4, 16, ARA_BATCH_PORTFOLIO_MAJOR};
     ara_status st = ARA_OK;
-    for (int ti = 0; ti < 4 && st == ARA_OK; ++ti)
-        for (int wi = 0; wi < 4 && st == ARA_OK; ++wi) {
-            ara_batch_config c = {tiles[ti], waves[wi]};
-            BatchPlan plan;
-            st = prep_batch(ctx, yet, n_portfolios, pfs, opts, &c, d_ylt_layers, d_ylt_portfolio,
-                            d_scratch, scratch_bytes, s, &plan);
-            if (st != ARA_OK) break;
-            hipError_t he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
-            if (he == hipSuccess) he = hipEventRecord(e0, s);
-            if (he == hipSuccess)
-                he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
-            if (he == hipSuccess) he = hipEventRecord(e1, s);
-            if (he == hipSuccess) he = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-            if (he != hipSuccess) {
-                st = fail(ctx, ARA_E_HIP, "ara_batch_autotune: %s", hipGetErrorString(he));
-                break;
+    bool warm = false;
+    for (int oi = 0; oi < 2 && st == ARA_OK; ++oi)
+        for (int ti = 0; ti < 3 && st == ARA_OK; ++ti)
+            for (int wi = 0; wi < 3 && st == ARA_OK; ++wi) {
+                ara_batch_config c = {tiles[ti], waves[wi], orders[oi]};
+                BatchPlan plan;
+                st = prep_batch(ctx, yet, n_portfolios, pfs, opts, &c, d_ylt_layers,
+                                d_ylt_portfolio, d_scratch, scratch_bytes, s, &plan);
+                if (st != ARA_OK) break;
+                hipError_t he = hipSuccess;
+                if (!warm) {
+                    he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+                    warm = true;
+                }
+                if (he == hipSuccess) he = hipEventRecord(e0, s);
+                if (he == hipSuccess)
+                    he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+                if (he == hipSuccess) he = hipEventRecord(e1, s);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                if (he != hipSuccess) {
+                    st = fail(ctx, ARA_E_HIP, "ara_batch_autotune: %s", hipGetErrorString(he));
+                    break;
+                }
+                if (ms < bms) {
+                    bms = ms;
+                    bc = c;
+                }
             }
-            if (ms < bms) {
-                bms = ms;
-                bc = c;
-            }
-        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != ARA_OK) return st;
@@ -866,17 +883,18 @@ namespace ara {
 ara_status run_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
                             ara_portfolio *const *pfs, const ara_run_opts *opts,
                             const ara_batch_config *cfg, void *const *ylt_l, void *const *ylt_p,
-                            const int64_t *ranges, void *scratch, size_t bytes, void *stream) {
+                            const int64_t *ranges, void *scratch, size_t bytes, void *stream,
+                            Status *status) {
     if (!ctx) return ARA_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     ARA_HIP(ctx, hipSetDevice(ctx->device));
     BatchPlan plan;
     ara_status st = prep_batch_ranges(ctx, yet, n, pfs, opts, cfg, ylt_l, ylt_p, ranges, scratch,
-                                      bytes, s, &plan);
+                                      bytes, s, status, &plan);
     if (st != ARA_OK) return st;
     ARA_HIP(ctx, launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s));
     return ARA_OK;
 }
-size_t batch_scratch_need(int32_t n, int64_t max_trials) { return batch_need(n, max_trials); }
+size_t batch_scratch_need(int32_t n, int64_t total_trials) { return batch_need(n, total_trials); }
 }  // namespace ara
 

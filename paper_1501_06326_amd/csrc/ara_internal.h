@@ -111,12 +111,15 @@ struct ara_portfolio {
 };
 
 namespace ara {
-// Batched run with a trial range per portfolio (ranges[2i], ranges[2i+1]);
-// defined with the C-ABI, used by the serving loop.
+// Batched run with a trial range per portfolio (ranges[2i], ranges[2i+1]),
+// portfolio-major; device-side errors go to *status (null: the context's own
+// status word).  Defined with the C-ABI, used by the serving loop.
 ara_status run_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
                             ara_portfolio *const *pfs, const ara_run_opts *opts,
                             const ara_batch_config *cfg, void *const *ylt_l, void *const *ylt_p,
-                            const int64_t *ranges, void *scratch, size_t bytes, void *stream);
-size_t batch_scratch_need(int32_t n, int64_t max_trials);
+                            const int64_t *ranges, void *scratch, size_t bytes, void *stream,
+                            Status *status);
+// Batch scratch for n portfolios whose trial ranges add up to total_trials.
+size_t batch_scratch_need(int32_t n, int64_t total_trials);
 }  // namespace ara
 

@@ -2,7 +2,7 @@
 batched launches on several streams, must give each request exactly the result
 it gets when submitted alone (bit for bit: YLT, PML and TVaR), and for a
 secondary-uncertainty portfolio the same YLT as ara_run; a pool too small for
-two requests at once still serves every request; a request that can never fit
+the largest request and any other at once still serves every request; a request that can never fit
 is refused at submission; a request with an invalid ELT fails alone."""
 import copy
 
@@ -102,18 +102,30 @@ def test_serve_matches_ara_run(setup):
         assert np.allclose(np.asarray(tvar), r["tvar"], rtol=1e-12, atol=0.0)
 
 
+def up(n):
+    return (n + 255) // 256 * 256
+
+
 def footprint(a, pf, count):
-    from paper_1501_06326_amd.ara import ara_batch_scratch_size, ara_pml_tvar_scratch_size
-    up = lambda n: (n + 255) // 256 * 256
+    """An upper bound of a request's pool region."""
+    from paper_1501_06326_amd.ara import ara_pml_tvar_scratch_size
     return (up(a.workspace_size(pf, N_CAT)) + up(4 * len(pf.layers) * count) + up(4 * count)
-            + up(ara_pml_tvar_scratch_size(count)) + up(ara_batch_scratch_size(1, count)))
+            + up(ara_pml_tvar_scratch_size(count)))
+
+
+def slot_scratch(slots, batch, n_trials):
+    from paper_1501_06326_amd.ara import ara_batch_scratch_size
+    return slots * up(ara_batch_scratch_size(batch, (n_trials + batch - 1) // batch))
 
 
 def test_serve_small_pool_serialises(setup):
     a, yet, y, pfs = setup
     say("serve small pool")
-    big = max(footprint(a, pfs[k], c) for k, b, c in REQS)
-    pool = big + big // 2            # room for one request at a time, not two
+    big = max(footprint(a, pfs[k], c) for k, b, c in REQS[:5])
+    small = min(footprint(a, pfs[k], c) for k, b, c in REQS[:5])
+    # room for the slots' scratch and the largest request, which then has the
+    # pool to itself: admission must hold the others back meanwhile
+    pool = slot_scratch(3, 4, 5000) + big + small // 2
     alone = serve(yet, pfs, REQS[:5], False, pool_bytes=256 << 20, max_inflight=3, max_batch=4)
     tight = serve(yet, pfs, REQS[:5], True, pool_bytes=pool, max_inflight=3, max_batch=4)
     for r0, r1 in zip(alone, tight):
@@ -127,7 +139,8 @@ def test_serve_refuses_request_that_never_fits(setup):
     say("serve refuse")
     from paper_1501_06326_amd import Server
     from paper_1501_06326_amd.ara import ARA_E_WORKSPACE_TOO_SMALL, AraError
-    with Server(yet, pool_bytes=footprint(a, pfs[0], 5000) // 2, max_inflight=1) as srv:
+    pool = slot_scratch(1, 1, 5000) + footprint(a, pfs[0], 5000) // 2
+    with Server(yet, pool_bytes=pool, max_inflight=1, max_batch=1) as srv:
         with pytest.raises(AraError) as e:
             srv.submit(pfs[0], 0, 5000, RPS)
         assert e.value.code == ARA_E_WORKSPACE_TOO_SMALL

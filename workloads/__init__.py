@@ -329,3 +329,40 @@ def batched_portfolios(n: int = 64, n_catalogue: int = 100_000, seed: int = 4,
         base += pf.n_elts
         out.append(pf)
     return out
+
+
+@dataclass
+class Request:
+    portfolio: Portfolio
+    trial_begin: int
+    trial_count: int
+
+
+def served_requests(n: int, n_trials: int, n_distinct: int = 32, n_catalogue: int = 100_000,
+                    seed: int = 5, sub_lo: int = 10_000, sub_hi: int = 1_000_000,
+                    su: bool = True) -> List[Request]:
+    """Serving workload: n requests cycling over n_distinct portfolios (layers
+    uniform 1-8, ELTs per layer uniform 2-32, rows log-uniform 1,000-50,000);
+    each request prices a contiguous trial range whose length is log-uniform on
+    [sub_lo, sub_hi] (clipped to the YET) with a uniformly random start."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed])))
+    pfs = []
+    base = 0
+    for _ in range(n_distinct):
+        pf = random_portfolio(rng, 1, 8, 2, 32, 1_000, 50_000, n_catalogue, base, su=su)
+        base += pf.n_elts
+        pfs.append(pf)
+    out = []
+    for i in range(n):
+        c = int(round(float(_log_uniform(rng, sub_lo, sub_hi))))
+        c = max(1, min(n_trials, c))
+        b = int(rng.integers(0, n_trials - c + 1))
+        out.append(Request(portfolio=pfs[int(rng.integers(0, n_distinct))], trial_begin=b,
+                           trial_count=c))
+    return out
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 6) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed])))
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
