@@ -17,6 +17,10 @@ Two further modes print their own JSON line:
   --mode batched  64 portfolios (1-16 layers, 2-48 ELTs per layer, 1,000-50,000
                   rows per ELT) on the same YET: one persistent batched launch
                   against 64 sequential ara_run calls.
+  --mode precision  8 layers (4-32 ELTs each, per-layer terms log-uniform on
+                  [1e5, 1e9]) on the same YET in the three sum modes: time per
+                  mode, and per-trial / PML / TVaR errors against the oracle on
+                  a sample of trials.
   --mode served   the serving loop under Poisson arrivals of requests (1-8
                   layers, 2-32 ELTs per layer, trial ranges of 1e4-1e6 trials):
                   p50 / p99 latency and throughput at several offered loads,
@@ -60,7 +64,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a known-size kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--mode", choices=["step", "batched", "served"], default="step")
+    ap.add_argument("--mode", choices=["step", "batched", "served", "precision"], default="step")
+    ap.add_argument("--oracle-trials", type=int, default=3000, help="precision mode")
     ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
     ap.add_argument("--graph", action="store_true", help="batched mode: also time a graph replay")
     ap.add_argument("--requests", type=int, default=1000, help="served mode: requests per load")
@@ -77,6 +82,8 @@ def main():
         return bench_batched(args)
     if args.mode == "served":
         return bench_served(args)
+    if args.mode == "precision":
+        return bench_precision(args)
 
     import torch
     from paper_1501_06326_amd import Ara, evaluations
@@ -312,6 +319,75 @@ def bench_batched(args):
         result["graph_equals_eager"] = all(torch.equal(a["ylt_pf"], b["ylt_pf"])
                                            for a, b in zip(gouts, outs))
         ara.graph_destroy(g)
+    print(json.dumps(result), flush=True)
+    ara.close()
+
+
+def bench_precision(args):
+    """Sum modes on the 8-layer precision-study portfolio: GPU time per mode and
+    error distributions against the oracle on the first --oracle-trials trials."""
+    import torch
+    import oracle
+    from paper_1501_06326_amd import Ara, evaluations
+    from workloads import multilayer_portfolio
+
+    yet = _full_yet(args.trials)
+    pf = multilayer_portfolio()
+    evals = evaluations(yet, pf)
+    ara = Ara(0)
+    dev = ara.device
+    off = torch.from_numpy(yet.offsets).to(dev)
+    ev = torch.from_numpy(yet.event_ids).to(dev)
+    y = ara.load_yet(yet, device_arrays=(off, ev, None))
+    p = ara.load_portfolio(pf, yet.n_catalogue)
+    m = min(args.oracle_trials, yet.n_trials)
+    t0 = time.time()
+    cores = len(os.sched_getaffinity(0))
+    ref = oracle.run_ara(yet, pf, 0, m, threads=cores)
+    log(f"oracle: {m} trials in {time.time() - t0:.1f}s on {cores} threads")
+    rps = [100.0, 250.0]
+    rp_ref, rt_ref = oracle.pml_tvar(ref["ylt_pf"], rps)
+    stream = torch.cuda.current_stream()
+    modes = {}
+    for mode in ("naive32", "kahan32", "f64"):
+        dt = "f64" if mode == "f64" else "f32"
+        r = ara.run(y, p, sum_mode=mode, ylt_dtype=dt)        # warmup and status check
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = ara.run(y, p, sum_mode=mode, ylt_dtype=dt, sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        g = r["ylt"][:, :m].double().cpu().numpy()
+        gp = r["ylt_pf"][:m].double().cpu().numpy()
+
+        def dist(err, scale, y_ref):
+            rel_g = err / np.maximum(scale, 1.0)
+            pos = y_ref > 0
+            rel_y = err[pos] / y_ref[pos] if pos.any() else np.zeros(1)
+            return {"max_over_G": float(rel_g.max()), "p99_over_G": _pct(rel_g, 99),
+                    "median_over_G": _pct(rel_g, 50), "max_rel": float(rel_y.max()),
+                    "p99_rel": _pct(rel_y, 99), "median_rel": _pct(rel_y, 50)}
+
+        layers = [dist(np.abs(g[l] - ref["ylt"][l]), ref["gross"][l], ref["ylt"][l])
+                  for l in range(len(pf.layers))]
+        port = dist(np.abs(gp - ref["ylt_pf"]), ref["gross"].sum(axis=0), ref["ylt_pf"])
+        pml, tvar = ara.pml_tvar(r["ylt_pf"][:m].contiguous(), rps)
+        modes[mode] = {
+            "ms_per_run": ms, "evaluations_per_s": evals / (ms / 1e3),
+            "layers": layers, "portfolio": port,
+            "pml_rel_err": [abs(a - b) / b for a, b in zip(pml, rp_ref)],
+            "tvar_rel_err": [abs(a - b) / b for a, b in zip(tvar, rt_ref)],
+        }
+        log(f"{mode}: {ms:.1f} ms, portfolio max err/G {port['max_over_G']:.3g}, "
+            f"PML err {modes[mode]['pml_rel_err']}")
+    result = {"metric": "precision study: per-trial and PML/TVaR errors by sum mode",
+              "n_gpus": 1, "data": "synthetic (seeded numpy generator; lognormal ELT means)",
+              "config": {"workload": f"ara_precision_8_layers_{yet.n_trials}_trials",
+                         "layers": len(pf.layers), "elts": pf.n_elts, "trials": yet.n_trials,
+                         "oracle_trials": m, "return_periods": rps,
+                         "evaluations_per_run": evals},
+              "modes": modes}
     print(json.dumps(result), flush=True)
     ara.close()
 

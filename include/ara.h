@@ -123,6 +123,17 @@ typedef struct {
     void *d_scratch;            /* optional: ara_run_scratch_size() bytes of device scratch;
                                    NULL = a buffer the context keeps (grown on demand) */
     size_t scratch_bytes;
+    void *d_occ_view;           /* optional occurrence view (section 2.2, aggregate terms):
+                                   element l * occ_view_stride + (j - offsets[trial_begin])
+                                   receives, for occurrence j of the run's trials, layer l's
+                                   increment d_j = A_j - A_{j-1} of the aggregate-term output
+                                   A_j = min(max(S_j - AggR, 0), AggL) over the running sum
+                                   S_j of the trial's occurrence losses in stored (time)
+                                   order; S_j in FP64; elements in opts->ylt_dtype.  A trial's
+                                   increments add up to its layer loss (up to rounding). */
+    int64_t occ_view_stride;    /* elements per layer of d_occ_view (>= the run's
+                                   occurrences; a larger index is not written and the run
+                                   reports ARA_E_WORKSPACE_TOO_SMALL through ara_sync_status) */
 } ara_run_opts;
 
 /* ---- context ------------------------------------------------------------ */
@@ -306,6 +317,21 @@ ara_status ara_pml_tvar_scratch_size(int64_t n, size_t *bytes);
 ara_status ara_pml_tvar(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, int64_t n,
                         const double *return_periods, int32_t n_rp, double *pml_out,
                         double *tvar_out, void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* Exceedance-probability curve (the return-period losses of section 2.3's
+ * reports) of the n losses in d_ylt (all >= 0): d_sorted[j] (n elements of
+ * ylt_dtype) receives the losses in descending order, so d_sorted[j] is the
+ * loss exceeded or equalled in a fraction (j+1)/n of the trials (return
+ * period n/(j+1)); d_tail_mean[j] (n doubles, may be NULL) the FP64 mean of
+ * d_sorted[0..j], the TVaR at that point.  For a return period RP with
+ * k = max(1, floor(n/RP)), d_sorted[k-1] and d_tail_mean[k-1] are the PML and
+ * TVaR of ara_pml_tvar.  -0.0 sorts as +0.0.  d_sorted may not alias d_ylt.
+ * d_scratch must hold ara_ep_curve_scratch_size(n, ylt_dtype) bytes.
+ * Asynchronous: enqueued on the stream. */
+ara_status ara_ep_curve_scratch_size(int64_t n, int32_t ylt_dtype, size_t *bytes);
+ara_status ara_ep_curve(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, int64_t n,
+                        void *d_sorted, double *d_tail_mean, void *d_scratch,
+                        size_t scratch_bytes, void *stream);
 
 /* ---- diagnostics (used by the tests) -------------------------------------
  * ara_debug_philox: d_out[4j..4j+3] = Philox4x32-10(d_ctr[4j..4j+3], key).

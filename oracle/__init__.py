@@ -242,3 +242,21 @@ def pml_tvar(ylt, return_periods):
     if rc != 0:
         raise ValueError("oracle pml_tvar: empty input")
     return pml, tvar
+
+
+def ep_curve(ylt):
+    """Exceedance-probability curve of a YLT (the return-period-loss report
+    of section 2.3): the losses in descending order (-0.0 taken as +0.0), so
+    entry j is the loss equalled or exceeded in a fraction (j+1)/N of the
+    trials, and the running means of the sorted losses (the TVaR at each
+    point), accumulated in extended precision.  At k = max(1, floor(N/RP))
+    entry k-1 is the PML / TVaR of ``pml_tvar``."""
+    y = np.asarray(ylt, np.float64).reshape(-1)
+    y = np.where(y == 0.0, 0.0, y)
+    srt = -np.sort(-y, kind="stable")
+    if srt.shape[0] == 0:
+        return srt, srt.copy()
+    cs = np.cumsum(srt.astype(np.longdouble))
+    tm = (cs / np.arange(1, srt.shape[0] + 1, dtype=np.longdouble)).astype(np.float64)
+    return srt, tm
+

@@ -41,7 +41,8 @@ EXPORTS = ["ara_create", "ara_destroy", "ara_status_string", "ara_last_error", "
            "ara_debug_beta_quantile", "ara_batch_scratch_size", "ara_run_batch",
            "ara_batch_autotune", "ara_batch_graph_create", "ara_graph_launch",
            "ara_graph_destroy", "ara_server_create", "ara_server_submit", "ara_server_poll",
-           "ara_server_release", "ara_server_destroy", "ara_server_last_error"]
+           "ara_server_release", "ara_server_destroy", "ara_server_last_error",
+           "ara_ep_curve_scratch_size", "ara_ep_curve"]
 
 SERVER_MAX_RP = 16
 
@@ -103,7 +104,8 @@ class ara_run_opts(C.Structure):
                 ("sum_mode", C.c_int32), ("ylt_dtype", C.c_int32),
                 ("tail_band", C.c_float), ("reserved", C.c_int32),
                 ("d_hits", C.c_void_p), ("d_hit_chk", C.c_void_p),
-                ("d_scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
+                ("d_scratch", C.c_void_p), ("scratch_bytes", C.c_size_t),
+                ("d_occ_view", C.c_void_p), ("occ_view_stride", C.c_int64)]
 
 
 _lib = None
@@ -160,6 +162,8 @@ def lib():
         L.ara_server_destroy.argtypes = [p]
         L.ara_server_last_error.argtypes = [p]
         L.ara_server_last_error.restype = C.c_char_p
+        L.ara_ep_curve_scratch_size.argtypes = [i64, i32, C.POINTER(sz)]
+        L.ara_ep_curve.argtypes = [p, p, i32, i64, p, p, p, sz, p]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is C.c_int:       # default
@@ -330,6 +334,19 @@ def ara_graph_destroy(ctx, graph) -> None:
     _check(ctx, lib().ara_graph_destroy(ctx, graph), "ara_graph_destroy")
 
 
+def ara_ep_curve_scratch_size(n: int, dtype: int) -> int:
+    b = C.c_size_t()
+    rc = lib().ara_ep_curve_scratch_size(int(n), int(dtype), C.byref(b))
+    if rc != ARA_OK:
+        raise AraError(rc, "ara_ep_curve_scratch_size")
+    return int(b.value)
+
+
+def ara_ep_curve(ctx, d_ylt, dtype, n, d_sorted, d_tail_mean, d_scratch, nbytes, stream):
+    _check(ctx, lib().ara_ep_curve(ctx, d_ylt, int(dtype), int(n), d_sorted, d_tail_mean,
+                                   d_scratch, nbytes, stream), "ara_ep_curve")
+
+
 def ara_server_create(device: int, n_trials: int, n_catalogue: int, d_offsets: int,
                       d_event_ids: int, cfg: "ara_server_config"):
     h = C.c_void_p()
@@ -425,9 +442,11 @@ class _Desc:
 
 
 class DeviceYET:
-    def __init__(self, handle, offsets, event_ids, times, n_trials, n_catalogue):
+    def __init__(self, handle, offsets, event_ids, times, n_trials, n_catalogue,
+                 offsets_host=None):
         self.handle = handle
         self.offsets, self.event_ids, self.times = offsets, event_ids, times
+        self.offsets_host = offsets_host
         self.n_trials, self.n_catalogue = n_trials, n_catalogue
 
 
@@ -482,7 +501,8 @@ class Ara:
         n_trials = int(off.shape[0] - 1)
         h = ara_load_yet(self.ctx, n_trials, int(yet.n_catalogue), _ptr(off), _ptr(ev), _ptr(tm),
                          _stream_handle(stream))
-        return DeviceYET(h, off, ev, tm, n_trials, int(yet.n_catalogue))
+        return DeviceYET(h, off, ev, tm, n_trials, int(yet.n_catalogue),
+                         np.asarray(yet.offsets, np.int64))
 
     def free_yet(self, y: DeviceYET):
         ara_free_yet(self.ctx, y.handle)
@@ -510,9 +530,11 @@ class Ara:
             trial_count: Optional[int] = None, sum_mode: str = "naive32",
             ylt_dtype: str = "f32", tail_band: float = 0.0, diagnostics: bool = False,
             out_layers=None, out_pf=None, stream=None, sync: bool = True,
-            layers: bool = True, scratch=None):
+            layers: bool = True, scratch=None, occ_view: bool = False,
+            occ_view_stride: Optional[int] = None):
         """``ara_run``; returns dict of device tensors ``ylt`` [n_layers, n]
-        and ``ylt_pf`` [n] (plus ``hits``/``hit_chk`` with diagnostics)."""
+        and ``ylt_pf`` [n] (plus ``hits``/``hit_chk`` with diagnostics, and
+        ``occ_view`` [n_layers, occurrences of the run] on request)."""
         t = self.torch
         if trial_count is None:
             trial_count = y.n_trials - trial_begin
@@ -525,12 +547,19 @@ class Ara:
         if diagnostics:
             hits = t.empty((p.n_layers, trial_count), dtype=t.int64, device=self.device)
             chk = t.empty((p.n_layers, trial_count), dtype=t.int64, device=self.device)
+        ov = None
+        if occ_view:
+            n_occ = int(y.offsets_host[trial_begin + trial_count] - y.offsets_host[trial_begin])
+            stride = n_occ if occ_view_stride is None else int(occ_view_stride)
+            ov = t.zeros((p.n_layers, max(1, stride)), dtype=dt, device=self.device)
         o = ara_run_opts(trial_begin=int(trial_begin), trial_count=int(trial_count),
                          sum_mode=SUM_MODES[sum_mode],
                          ylt_dtype=ARA_F64 if ylt_dtype == "f64" else ARA_F32,
                          tail_band=float(tail_band), reserved=0, d_hits=_ptr(hits),
                          d_hit_chk=_ptr(chk), d_scratch=_ptr(scratch),
-                         scratch_bytes=0 if scratch is None else scratch.numel())
+                         scratch_bytes=0 if scratch is None else scratch.numel(),
+                         d_occ_view=_ptr(ov),
+                         occ_view_stride=0 if ov is None else int(ov.shape[1]))
         s = _stream_handle(stream)
         ara_run(self.ctx, y.handle, p.handle, o, _ptr(out_layers), _ptr(out_pf), s)
         if sync:
@@ -538,7 +567,24 @@ class Ara:
         res = {"ylt": out_layers, "ylt_pf": out_pf}
         if diagnostics:
             res["hits"], res["hit_chk"] = hits, chk
+        if ov is not None:
+            res["occ_view"] = ov
         return res
+
+    def ep_curve(self, ylt, tail_mean: bool = True, stream=None):
+        """``ara_ep_curve``: (losses in descending order, FP64 running means or
+        None) as device tensors."""
+        t = self.torch
+        y = ylt.contiguous()
+        n = int(y.numel())
+        dtype = ARA_F64 if y.dtype == t.float64 else ARA_F32
+        srt = t.empty(n, dtype=y.dtype, device=self.device)
+        tm = t.empty(n, dtype=t.float64, device=self.device) if tail_mean else None
+        sz = ara_ep_curve_scratch_size(n, dtype)
+        sc = t.empty(max(1, sz), dtype=t.uint8, device=self.device)
+        ara_ep_curve(self.ctx, _ptr(y), dtype, n, _ptr(srt), _ptr(tm), _ptr(sc), sz,
+                     _stream_handle(stream))
+        return srt, tm
 
     def run_scratch_size(self, trial_count: int) -> int:
         return ara_run_scratch_size(trial_count)

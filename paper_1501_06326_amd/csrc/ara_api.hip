@@ -147,6 +147,10 @@ ara_status check_status(ara_context *ctx, hipStream_t s, const char *what) {
     case ARA_E_BAD_ELT_ROW:
         return fail(ctx, h.code, "%s: bad ELT row %lld%s", what, (long long)h.where[1],
                     h.where[0] == -2 ? " (duplicate event in one ELT)" : "");
+    case ARA_E_WORKSPACE_TOO_SMALL:
+        return fail(ctx, h.code, "%s: occurrence view stride %lld too small (trial %lld needs "
+                                 "index %lld)", what, (long long)h.where[2], (long long)h.where[0],
+                    (long long)h.where[1]);
     case ARA_E_NUMERIC:
         return fail(ctx, h.code, "%s: Beta quantile did not converge (trial %lld, occurrence %lld, "
                                  "elt_id %lld)", what, (long long)h.where[0], (long long)h.where[1],
@@ -459,6 +463,8 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
     if (o.trial_count > 0x7fffffff)
         return fail(ctx, ARA_E_UNSUPPORTED, "ara_run: more than 2^31 trials in one run");
     if (!(o.tail_band > 0.0f)) o.tail_band = kDefaultTailBand;
+    if (o.d_occ_view && o.occ_view_stride <= 0)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run: occurrence view without a positive stride");
     if (o.trial_count == 0 || pf->n_layers == 0) {
         hipStream_t s = (hipStream_t)stream;
         const size_t es = o.ylt_dtype == ARA_F64 ? 8 : 4;
@@ -493,6 +499,9 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
             p.ylt_layers = d_ylt_layers;
             p.ylt_pf = d_ylt_portfolio;
             p.accumulate_pf = l > 0;
+            p.occ_view = o.d_occ_view;
+            p.occ_stride = o.occ_view_stride;
+            p.status = ctx->d_status;
             int64_t blocks = (o.trial_count + 3) / 4;
             int64_t g = blocks < (int64_t)ctx->n_cu * 16 ? blocks : (int64_t)ctx->n_cu * 16;
             p.grid = (int)(g < 1 ? 1 : g);
@@ -520,6 +529,8 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
     p.ylt_pf = d_ylt_portfolio;
     p.hits = o.d_hits;
     p.hit_chk = o.d_hit_chk;
+    p.occ_view = o.d_occ_view;
+    p.occ_stride = o.occ_view_stride;
     p.status = ctx->d_status;
     const size_t need = run_scratch_need(o.trial_count);
     char *scr = (char *)o.d_scratch;
@@ -595,6 +606,29 @@ ara_status ara_pml_tvar(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, 
     return ARA_OK;
 }
 
+ara_status ara_ep_curve_scratch_size(int64_t n, int32_t ylt_dtype, size_t *bytes) {
+    if (!bytes || n < 0 || (ylt_dtype != ARA_F32 && ylt_dtype != ARA_F64)) return ARA_E_INVALID_ARG;
+    *bytes = ep_scratch_bytes(n, ylt_dtype);
+    return ARA_OK;
+}
+
+ara_status ara_ep_curve(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, int64_t n,
+                        void *d_sorted, double *d_tail_mean, void *d_scratch,
+                        size_t scratch_bytes, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!d_ylt || !d_sorted)) || d_sorted == d_ylt ||
+        (ylt_dtype != ARA_F32 && ylt_dtype != ARA_F64) || n > 0xffffffffll)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_ep_curve: bad arguments");
+    if (n == 0) return ARA_OK;
+    const size_t need = ep_scratch_bytes(n, ylt_dtype);
+    if (!d_scratch || scratch_bytes < need)
+        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_ep_curve: need %zu scratch bytes", need);
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    ARA_HIP(ctx, launch_ep_curve(d_ylt, ylt_dtype, n, d_sorted, d_tail_mean, d_scratch,
+                                 (hipStream_t)stream));
+    return ARA_OK;
+}
+
 // ---- batched portfolios ----------------------------------------------------
 namespace {
 
@@ -629,8 +663,9 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     if (o.sum_mode < ARA_SUM_NAIVE32 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
         o.ylt_dtype > ARA_F64)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad sum_mode or ylt_dtype");
-    if (o.d_hits || o.d_hit_chk)
-        return fail(ctx, ARA_E_UNSUPPORTED, "ara_run_batch: hit diagnostics are per-portfolio only");
+    if (o.d_hits || o.d_hit_chk || o.d_occ_view)
+        return fail(ctx, ARA_E_UNSUPPORTED,
+                    "ara_run_batch: hit diagnostics and the occurrence view are per-portfolio only");
     if (!(o.tail_band > 0.0f)) o.tail_band = kDefaultTailBand;
     ara_batch_config c = {4, 16, ARA_BATCH_TRIAL_MAJOR};
     if (cfg) {

@@ -24,6 +24,9 @@ struct PuLaunch {
     void *ylt_pf;
     int32_t accumulate_pf;      // 0: ylt_pf = Y, 1: ylt_pf += Y
     int grid;
+    void *occ_view;             // optional occurrence view (see ara_run_opts)
+    int64_t occ_stride;
+    Status *status;
 };
 
 struct SuLaunch {
@@ -49,6 +52,8 @@ struct SuLaunch {
     int32_t *redo;            // [trial_count] scratch: trials handed to the FP64-capable pass
     uint32_t *redo_count;     // scratch counter
     int redo_grid;            // blocks of the second pass
+    void *occ_view;           // optional occurrence view (see ara_run_opts)
+    int64_t occ_stride;
 };
 
 // One portfolio of a batched run (device array of these).
@@ -109,8 +114,11 @@ hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, cons
                                  const double *zc, float tail, float *x, int32_t *path,
                                  hipStream_t s);
 
-// PML / TVaR (ara_select.hip)
+// PML / TVaR and the exceedance-probability curve (ara_select.hip)
 size_t pml_scratch_bytes(int64_t n);
+size_t ep_scratch_bytes(int64_t n, int32_t dtype);
+hipError_t launch_ep_curve(const void *ylt, int32_t dtype, int64_t n, void *sorted,
+                           double *tail_mean, void *scratch, hipStream_t s);
 hipError_t launch_pml_tvar(const void *ylt, int32_t dtype, int64_t n, const int64_t *ks, int32_t n_rp,
                            void *scratch, double *d_out /* [2 * n_rp]: pml, tvar */, hipStream_t s);
 

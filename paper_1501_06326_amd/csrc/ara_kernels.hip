@@ -361,9 +361,66 @@ struct PuArgs {
     int32_t layer;
     void *ylt_layers, *ylt_pf;
     int32_t accumulate_pf;
+    void *occ_view;
+    int64_t occ_stride;
+    Status *status;
 };
 
 enum { TAB_GLOBAL = 0, TAB_LDS_DENSE = 1, TAB_LDS_SPARSE = 2 };
+
+// Occurrence view of 64 consecutive occurrences of one trial and layer, in
+// stored order: o (lane's occurrence loss net of the occurrence terms, 0 past
+// the end) is scanned into the running sum S (FP64, carried in *cs), the
+// aggregate terms give A = min(max(S - AggR, 0), AggL) (carried in *ca), and
+// the lane's increment A - A_prev is written at pos when valid.  Every lane
+// of the wave calls this (the scan reads all of them).
+template <bool F64OUT>
+__device__ __forceinline__ void occ_chunk(double o, bool valid, int64_t pos, int layer,
+                                          void *view, int64_t stride, float agg_r, float agg_l,
+                                          double *cs, double *ca, Status *st, int64_t trial) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double v = __shfl_up(o, d, 64);
+        if (lane >= d) o += v;
+    }
+    const double S = *cs + o;
+    const double A = clampd_terms(S, (double)agg_r, (double)agg_l);
+    double Ap = __shfl_up(A, 1, 64);
+    if (lane == 0) Ap = *ca;
+    if (valid) {
+        if (pos < stride) {
+            const int64_t at = (int64_t)layer * stride + pos;
+            if (F64OUT) ((double *)view)[at] = A - Ap;
+            else ((float *)view)[at] = (float)(A - Ap);
+        } else {
+            report(st, ARA_E_WORKSPACE_TOO_SMALL, trial, pos, stride);
+        }
+    }
+    *cs = __shfl(S, 63, 64);
+    *ca = __shfl(A, 63, 64);
+}
+
+// Occurrence view of a primary-uncertainty layer (one wavefront per trial):
+// the per-event occurrence losses of the layer's table, in stored order.
+template <bool F64OUT>
+__global__ __launch_bounds__(256) void k_pu_occ_view(PuArgs P) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t nwv = (int64_t)gridDim.x * (blockDim.x / 64);
+    const int64_t base = P.off[P.trial_begin];
+    for (int64_t t = wid; t < P.trial_count; t += nwv) {
+        const int64_t a = P.off[P.trial_begin + t], b = P.off[P.trial_begin + t + 1];
+        double cs = 0.0, ca = 0.0;
+        for (int64_t c = a; c < b; c += 64) {
+            const int64_t j = c + lane;
+            const bool valid = j < b;
+            const double o = valid ? (double)P.otab[P.ev[j]] : 0.0;
+            occ_chunk<F64OUT>(o, valid, j - base, P.layer, P.occ_view, P.occ_stride, P.agg_r,
+                              P.agg_l, &cs, &ca, P.status, P.trial_begin + t);
+        }
+    }
+}
 
 // One wavefront per trial (persistent grid-stride over trials).  Event ids
 // are streamed with 16-byte loads (after a scalar head that reaches 16-byte
@@ -469,6 +526,8 @@ struct SuArgs {
     Status *status;
     int32_t *redo;            // trials (relative index) handed to the FP64-capable pass
     uint32_t *redo_count;
+    void *occ_view;           // occurrence view, written by the DIAG instantiations only
+    int64_t occ_stride;
 };
 
 // The draws of a hit as 24-bit grid integers: jI keyed (k, i, elt_id, 0),
@@ -526,6 +585,9 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
         Acc<MODE> acc;
         uint64_t chk = 0;
         int64_t nh = 0;
+        double occ_s = 0.0, occ_a = 0.0;      // occurrence-view carries
+        (void)occ_s;
+        (void)occ_a;
 
         for (int64_t seg = 0; seg < n; seg += kSeg) {
             const int segn = (int)((n - seg) < kSeg ? (n - seg) : kSeg);
@@ -629,6 +691,16 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
             __syncthreads();
             for (int i = lane; i < segn; i += kWave)
                 acc.add(clampf_terms(X[i], L.occ_r, L.occ_l));
+            if (DIAG && A.occ_view) {
+                const int64_t pos0 = o0 - A.off[A.trial_begin] + seg;
+                for (int c = 0; c < segn; c += kWave) {
+                    const int i = c + lane;
+                    const bool valid = i < segn;
+                    const double o = valid ? (double)clampf_terms(X[i], L.occ_r, L.occ_l) : 0.0;
+                    occ_chunk<F64OUT>(o, valid, pos0 + i, l, A.occ_view, A.occ_stride, L.agg_r,
+                                      L.agg_l, &occ_s, &occ_a, A.status, ti);
+                }
+            }
             __syncthreads();
         }
 
@@ -719,6 +791,8 @@ __device__ __forceinline__ void batch_view(const BatchArgs &B, int p, SuArgs &A,
     A.status = B.status;
     A.redo = nullptr;
     A.redo_count = nullptr;
+    A.occ_view = nullptr;
+    A.occ_stride = 0;
     keys.k0 = P.k0;
     keys.k1 = P.k1;
 }
@@ -896,6 +970,9 @@ static hipError_t pu_dispatch(const PuLaunch &p, hipStream_t s) {
     A.otab = p.otab; A.sp_bits = p.sp_bits; A.sp_rank = p.sp_rank; A.sp_vals = p.sp_vals;
     A.nnz = p.nnz; A.n_cat = p.n_cat; A.agg_r = p.agg_r; A.agg_l = p.agg_l; A.layer = p.layer;
     A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf; A.accumulate_pf = p.accumulate_pf;
+    A.occ_view = p.occ_view; A.occ_stride = p.occ_stride; A.status = p.status;
+    if (p.occ_view)
+        hipLaunchKernelGGL((k_pu_occ_view<F64OUT>), dim3(p.grid), dim3(256), 0, s, A);
     const size_t nw = ((size_t)p.n_cat + 31) / 32;
     const size_t dense = (size_t)p.n_cat * sizeof(float);
     const size_t sparse = (2 * nw + 1 + (size_t)p.nnz) * sizeof(uint32_t);
@@ -928,11 +1005,12 @@ static hipError_t su_dispatch2(const SuLaunch &p, hipStream_t s) {
     A.tail_band = p.tail_band; A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf;
     A.hits = p.hits; A.hit_chk = p.hit_chk; A.status = p.status;
     A.redo = p.redo; A.redo_count = p.redo_count;
+    A.occ_view = p.occ_view; A.occ_stride = p.occ_stride;
     const PhiloxKeys keys = philox_keys(p.seed);
     // a kernel, not hipMemsetAsync, so the sequence can be captured in a graph
     hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(1), 0, s, p.redo_count);
     const dim3 g((unsigned)p.trial_count), gr((unsigned)p.redo_grid);
-    if (p.hits || p.hit_chk) {
+    if (p.hits || p.hit_chk || p.occ_view) {
         hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, true>), g, dim3(64), 0, s, A, keys);
         hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, true>), gr, dim3(64), 0, s, A, keys);
     } else {

@@ -7,6 +7,13 @@
 // step per digit.  TVaR(RP) is the mean of the k largest losses: the sum of
 // the losses strictly above the PML plus (k - their count) copies of the
 // PML, accumulated in FP64 with a fixed reduction order (deterministic).
+//
+// The exceedance-probability curve (the return-period losses of the report
+// the paper names) is the whole YLT in descending order: a stable
+// least-significant-digit radix sort over the inverted key patterns (8-bit
+// digits; per pass a block histogram, one scan of the digit-major counts, and
+// a scatter that ranks equal digits by wavefront ballots), followed by FP64
+// running means of the sorted losses (the TVaR at every point).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -160,6 +167,224 @@ static hipError_t run_select(const T *y, int64_t n, const int64_t *ks, int32_t n
         hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(1), 0, s, st, psum, pcnt, gs, d_out, r, n_rp);
     }
     return hipGetLastError();
+}
+
+// ---- exceedance-probability curve ------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortIpt = 8;
+constexpr int kSortTile = kSortThreads * kSortIpt;   // keys per block and pass
+
+template <typename T>
+__global__ void k_sort_keys(const T *__restrict__ y, int64_t n, typename KeyOf<T>::K *__restrict__ keys) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        keys[i] = ~KeyOf<T>::key(y[i]);          // ascending inverted = descending losses
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K *__restrict__ keys, int64_t n,
+                                                            int shift, uint32_t *__restrict__ counts,
+                                                            int nb) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortIpt; ++r) {
+        const int64_t i = t0 + (int64_t)r * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of c[0, m) in place: one block, a serial chunk per thread.
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ c, int64_t m) {
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (m + 1023) / 1024;
+    const int64_t b = (int64_t)tid * chunk, e = (b + chunk) < m ? (b + chunk) : m;
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += c[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = tid >= d ? part[tid - d] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = tid ? part[tid - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t v = c[i];
+        c[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter of one digit: the block's keys in kSortIpt rounds of 256 (in
+// index order); in a round each wavefront finds the lanes sharing a lane's
+// digit with eight ballots, the lowest of them records the count, and a key
+// lands at its digit's block offset + the keys of that digit in earlier
+// rounds and earlier wavefronts + its rank among its wavefront's equals.
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restrict__ in,
+                                                               K *__restrict__ out, int64_t n,
+                                                               int shift,
+                                                               const uint32_t *__restrict__ offs,
+                                                               int nb) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kSortThreads / 64][256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    for (int q = 0; q < kSortThreads / 64; ++q) wcnt[q][tid] = 0u;
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortIpt; ++r) {
+        const int64_t i = t0 + (int64_t)r * kSortThreads + tid;
+        const bool valid = i < n;
+        const K k = valid ? in[i] : (K)0;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t b = __ballot(valid && on);
+            m &= on ? b : ~b;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & below);
+        if (valid && rank == 0u) wcnt[w][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[d] + rank;
+            for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+            out[pos] = k;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int q = 0; q < kSortThreads / 64; ++q) {
+            add += wcnt[q][tid];
+            wcnt[q][tid] = 0u;
+        }
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void k_sort_values(typename KeyOf<T>::K *__restrict__ keys, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = KeyOf<T>::value(~keys[i]);
+        reinterpret_cast<T *>(keys)[i] = (T)v;
+    }
+}
+
+// Running means of the sorted losses in FP64: block sums, a scan of them, and
+// a block-local scan (a serial run of kSortIpt per thread).
+template <typename T>
+__global__ __launch_bounds__(kSortThreads) void k_tm_partial(const T *__restrict__ v, int64_t n,
+                                                             double *__restrict__ part) {
+    __shared__ double s[kSortThreads];
+    const int64_t b0 = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortIpt;
+    double acc = 0.0;
+    for (int j = 0; j < kSortIpt; ++j)
+        if (b0 + j < n) acc += (double)v[b0 + j];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = kSortThreads / 2; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d) s[threadIdx.x] += s[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_tm_scan(double *__restrict__ part, int nb) {
+    double run = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double v = part[b];
+        part[b] = run;
+        run += v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSortThreads) void k_tm_final(const T *__restrict__ v, int64_t n,
+                                                           const double *__restrict__ part,
+                                                           double *__restrict__ tm) {
+    __shared__ double s[kSortThreads];
+    const int tid = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * kSortTile + (int64_t)tid * kSortIpt;
+    double acc = 0.0;
+    for (int j = 0; j < kSortIpt; ++j)
+        if (b0 + j < n) acc += (double)v[b0 + j];
+    s[tid] = acc;
+    __syncthreads();
+    for (int d = 1; d < kSortThreads; d <<= 1) {
+        const double x = tid >= d ? s[tid - d] : 0.0;
+        __syncthreads();
+        s[tid] += x;
+        __syncthreads();
+    }
+    double run = part[blockIdx.x] + (tid ? s[tid - 1] : 0.0);
+    for (int j = 0; j < kSortIpt; ++j) {
+        const int64_t i = b0 + j;
+        if (i < n) {
+            run += (double)v[i];
+            tm[i] = run / (double)(i + 1);
+        }
+    }
+}
+
+static int sort_blocks(int64_t n) { return (int)((n + kSortTile - 1) / kSortTile); }
+
+size_t ep_scratch_bytes(int64_t n, int32_t dtype) {
+    const size_t ks = dtype == ARA_F64 ? 8 : 4;
+    const size_t nb = (size_t)sort_blocks(n > 0 ? n : 1);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return up(ks * (size_t)(n > 0 ? n : 1)) + up(sizeof(uint32_t) * 256 * nb) + up(sizeof(double) * nb);
+}
+
+template <typename T>
+static hipError_t run_ep(const T *y, int64_t n, T *sorted, double *tail_mean, void *scratch,
+                         hipStream_t s) {
+    using K = typename KeyOf<T>::K;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int nb = sort_blocks(n);
+    char *p = (char *)scratch;
+    K *tmp = (K *)p;
+    uint32_t *counts = (uint32_t *)(p + up(sizeof(K) * (size_t)n));
+    double *part = (double *)((char *)counts + up(sizeof(uint32_t) * 256 * (size_t)nb));
+    K *keys = (K *)sorted;                        // the output doubles as a key buffer
+    const int g = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL((k_sort_keys<T>), dim3(g), dim3(256), 0, s, y, n, keys);
+    K *a = keys, *b = tmp;
+    for (int shift = 0; shift < KeyOf<T>::bits; shift += 8) {   // an even number of passes
+        hipLaunchKernelGGL((k_sort_hist<K>), dim3(nb), dim3(kSortThreads), 0, s, a, n, shift,
+                           counts, nb);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, (int64_t)256 * nb);
+        hipLaunchKernelGGL((k_sort_scatter<K>), dim3(nb), dim3(kSortThreads), 0, s, a, b, n,
+                           shift, counts, nb);
+        K *t = a;
+        a = b;
+        b = t;
+    }
+    hipLaunchKernelGGL((k_sort_values<T>), dim3(g), dim3(256), 0, s, keys, n);
+    if (tail_mean) {
+        hipLaunchKernelGGL((k_tm_partial<T>), dim3(nb), dim3(kSortThreads), 0, s, sorted, n, part);
+        hipLaunchKernelGGL(k_tm_scan, dim3(1), dim3(1), 0, s, part, nb);
+        hipLaunchKernelGGL((k_tm_final<T>), dim3(nb), dim3(kSortThreads), 0, s, sorted, n, part,
+                           tail_mean);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ep_curve(const void *ylt, int32_t dtype, int64_t n, void *sorted,
+                           double *tail_mean, void *scratch, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (dtype == ARA_F64)
+        return run_ep<double>((const double *)ylt, n, (double *)sorted, tail_mean, scratch, s);
+    return run_ep<float>((const float *)ylt, n, (float *)sorted, tail_mean, scratch, s);
 }
 
 hipError_t launch_pml_tvar(const void *ylt, int32_t dtype, int64_t n, const int64_t *ks, int32_t n_rp,

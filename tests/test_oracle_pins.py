@@ -530,6 +530,38 @@ def test_pml_tvar_brute_force(case):
         assert abs(tvar[j] - t) <= 1e-15 * abs(t)
 
 
+@pytest.mark.parametrize("case", ["random", "ties", "zeros", "tiny"])
+def test_ep_curve_exact(case):
+    """EP curve: descending order and running means against exact rational
+    arithmetic, and agreement with the independent C PML / TVaR."""
+    from fractions import Fraction
+    rng = np.random.default_rng(4)
+    if case == "random":
+        y = rng.lognormal(14, 2, size=3000)
+    elif case == "ties":
+        y = np.repeat(rng.lognormal(14, 2, size=30), 40)
+    elif case == "zeros":
+        y = np.array([0.0, -0.0, 0.0, 5.0])
+    else:
+        y = rng.lognormal(3, 1, size=7)
+    srt, tm = O.ep_curve(y)
+    ref = sorted([float(v) for v in y], reverse=True)
+    assert [float(v) for v in srt] == ref
+    assert np.all(np.signbit(srt) == False)          # noqa: E712  (-0.0 folded)
+    run = Fraction(0)
+    for j, v in enumerate(ref):
+        run += Fraction(v)
+        exact = run / (j + 1)
+        assert abs(Fraction(float(tm[j])) - exact) <= Fraction(1, 10 ** 15) * abs(exact)
+    assert np.all(np.diff(srt) <= 0) and np.all(tm[:-1] >= tm[1:] - 1e-9 * tm[1:])
+    rps = [1.0, 2.0, 10.0, 100.0, 1e9]
+    pml, tvar = O.pml_tvar(y, rps)
+    for j, rp in enumerate(rps):
+        k = max(1, int(math.floor(len(y) / rp)))
+        assert pml[j] == srt[k - 1]
+        assert abs(tvar[j] - tm[k - 1]) <= 1e-15 * abs(tvar[j])
+
+
 # --------------------------------------------------------------------------
 # P14: hit counts of the direct-access lookups
 # --------------------------------------------------------------------------
