@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--trials", type=int, default=1_000_000)
+    ap.add_argument("--catalogue", type=int, default=100_000,
+                    help="events in the catalogue (1,000,000: the large-catalogue variant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -90,7 +92,7 @@ def main():
     from workloads import config_full, full_portfolio
 
     t0 = time.time()
-    w = config_full(n_trials=args.trials)
+    w = config_full(n_trials=args.trials, n_catalogue=args.catalogue)
     yet, pf = w.yet, w.portfolio
     log(f"generated {w.name}: {yet.n_occ} occurrences in {time.time() - t0:.1f}s")
     evals = evaluations(yet, pf)
@@ -181,7 +183,7 @@ def main():
     }
 
     if not args.no_pu:
-        pf_pu = full_portfolio(su=False)
+        pf_pu = full_portfolio(su=False, n_catalogue=args.catalogue)
         p_pu = ara.load_portfolio(pf_pu, yet.n_catalogue)
         for _ in range(3):
             ara.run(y, p_pu, out_layers=out_l, out_pf=out_p, sync=False)

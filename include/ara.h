@@ -103,11 +103,25 @@ typedef struct {
     uint32_t program_id;        /* label only */
 } ara_layer_desc;
 
+/* How the two uniforms of section 3.2 are keyed (Philox4x32-10 counter words
+ * (c0, c1, c2, c3), key = the portfolio seed; k = occurrence index in the
+ * trial, i = absolute trial index, E = event id):
+ *   ARA_KEYING_OCCURRENCE (default): u_I at (k, i, elt_id, 0), independent
+ *     per ELT; u_C at (k, i, 0, 1), shared by every ELT of the occurrence.
+ *   ARA_KEYING_PAPER (the inputs of section 3.1 as laid out there): u_I is
+ *     z_(Prog,E), one per occurrence and program, at (k, i, program_id, 2),
+ *     shared by all ELTs of the program's layers; u_C is z_(E), the value an
+ *     XELT row holds for its event, the same in every occurrence, ELT and
+ *     program, at (E, 0, 0, 3). */
+#define ARA_KEYING_OCCURRENCE 0
+#define ARA_KEYING_PAPER 1
+
 typedef struct {
     int32_t n_layers;
     const ara_layer_desc *layers;
     uint64_t seed;              /* Philox key */
     int32_t su_enabled;         /* 0: primary uncertainty only (mean losses) */
+    int32_t keying;             /* ARA_KEYING_* */
 } ara_portfolio_desc;
 
 typedef struct {

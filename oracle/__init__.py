@@ -51,8 +51,11 @@ def lib():
         L.orc_beta_fit.argtypes = [_dbl, _dbl, _dbl, _p, _p]
         L.orc_su_loss.argtypes = [_dbl, _dbl, _dbl, _dbl, _u32, _u32, _u32, _u64]
         L.orc_su_loss.restype = _dbl
+        L.orc_su_loss_keyed.argtypes = [_dbl, _dbl, _dbl, _dbl, _u32, _u32, _u32, _u32, _u32,
+                                        _i32, _u64]
+        L.orc_su_loss_keyed.restype = _dbl
         L.orc_ara_run.argtypes = [_i64, _i64, _p, _p, _i32, _i32, _p, _i32, _p, _p, _p, _p,
-                                  _p, _p, _p, _p, _p, _u64, _i32, _i32,
+                                  _p, _p, _p, _p, _p, _u64, _i32, _i32, _p, _i32,
                                   _p, _p, _p, _p, _p, _p]
         L.orc_ara_run.restype = _i32
         L.orc_pml_tvar.argtypes = [_p, _i64, _p, _i32, _p, _p]
@@ -141,6 +144,13 @@ def beta_fit(mu: float, sigma: float, max_l: float):
     return a.value, b.value
 
 
+def su_loss_keyed(mu, s_i, s_c, max_l, k, i, elt_id, program, event, keying, seed: int):
+    """One hit's loss under either keying (scalar arguments)."""
+    return lib().orc_su_loss_keyed(float(mu), float(s_i), float(s_c), float(max_l), int(k),
+                                   int(i), int(elt_id), int(program), int(event), int(keying),
+                                   int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
 def su_loss(mu, s_i, s_c, max_l, k, i, elt_id, seed: int) -> np.ndarray:
     arrs = np.broadcast_arrays(*(np.asarray(v) for v in (mu, s_i, s_c, max_l, k, i, elt_id)))
     mu, s_i, s_c, max_l = (_c(v, np.float64).reshape(-1) for v in arrs[:4])
@@ -155,12 +165,13 @@ def su_loss(mu, s_i, s_c, max_l, k, i, elt_id, seed: int) -> np.ndarray:
 # ARA run and risk metrics
 # --------------------------------------------------------------------------
 def _flatten_portfolio(pf):
-    layer_terms = []
+    layer_terms, layer_program = [], []
     elt_layer, elt_id, elt_terms, row_off = [], [], [], [0]
     ev, mu, si, sc, mx = [], [], [], [], []
     for li, layer in enumerate(pf.layers):
         layer_terms += [layer.occ_retention, layer.occ_limit,
                         layer.agg_retention, layer.agg_limit]
+        layer_program.append(int(getattr(layer, "program_id", 0)) & 0xFFFFFFFF)
         for elt in layer.elts:
             elt_layer.append(li)
             elt_id.append(elt.elt_id)
@@ -178,6 +189,7 @@ def _flatten_portfolio(pf):
 
     return dict(
         layer_terms=np.asarray(layer_terms, np.float64),
+        layer_program=np.asarray(layer_program, np.uint32),
         elt_layer=np.asarray(elt_layer, np.int32),
         elt_id=np.asarray(elt_id, np.uint32),
         elt_terms=np.asarray(elt_terms, np.float64),
@@ -223,7 +235,8 @@ def run_ara(yet, pf, trial_begin: int = 0, trial_count: Optional[int] = None,
         n, trial_begin, _ptr(off), _ptr(ids), int(yet.n_catalogue), L, _ptr(f["layer_terms"]),
         len(f["elt_layer"]), _ptr(f["elt_layer"]), _ptr(f["elt_id"]), _ptr(f["row_off"]),
         _ptr(f["elt_terms"]), _ptr(f["ev"]), _ptr(f["mu"]), _ptr(f["si"]), _ptr(f["sc"]),
-        _ptr(f["mx"]), int(pf.seed) & 0xFFFFFFFFFFFFFFFF, 1 if pf.su_enabled else 0, int(nthr),
+        _ptr(f["mx"]), int(pf.seed) & 0xFFFFFFFFFFFFFFFF, 1 if pf.su_enabled else 0,
+        int(getattr(pf, "keying", 0)), _ptr(f["layer_program"]), int(nthr),
         _ptr(ylt), _ptr(ylt_pf), _ptr(gross), _ptr(hits), _ptr(chk), _ptr(ov))
     if rc != 0:
         raise ValueError(f"oracle rejected the inputs (code {rc})")

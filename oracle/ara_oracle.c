@@ -40,6 +40,12 @@
  *   R9  Both z and its complement 1 - z are carried, the complement computed
  *       directly (1 - u on the draw grid, Phi(-v) after the normal mix), so
  *       upper-tail quantiles keep full relative accuracy.
+ *   R10 Optional keying that follows the input layout of section 3.1: the
+ *       independent draw is z_(Prog,E), one per occurrence and program,
+ *       counter (k, i, program_id, 2), shared by every ELT of the program's
+ *       layers; the correlated draw is z_(E), a value held per XELT row for
+ *       its event and the same in every occurrence, ELT and program, counter
+ *       (E, 0, 0, 3).  (R4 is the default keying.)
  *
  * Numerics: Phi from erfc; Phi^-1 by bracketed Newton on that Phi; I_x(a,b)
  * by the continued fraction of DLMF 8.17.22 (modified Lentz) with the
@@ -295,29 +301,43 @@ static void combine_sigma(double u_pe, double u_e, double s_i, double s_c,
     *zc = orc_norm_cdf(-v);
 }
 
-/* Loss of one ELT row hit by occurrence k of trial i (secondary uncertainty
- * on), section 3: draw, combine, fit, invert, scale by max_l. */
-double orc_su_loss(double mu, double s_i, double s_c, double max_l,
-                   uint32_t k, uint32_t i, uint32_t elt_id, uint64_t seed)
+/* Loss of one ELT row hit by occurrence k (event E) of trial i (secondary
+ * uncertainty on), section 3: draw, combine, fit, invert, scale by max_l.
+ * keying 0: R4; keying 1: R10 (program = the layer's program id). */
+double orc_su_loss_keyed(double mu, double s_i, double s_c, double max_l,
+                         uint32_t k, uint32_t i, uint32_t elt_id, uint32_t program,
+                         uint32_t event, int32_t keying, uint64_t seed)
 {
     double sigma = s_i + s_c;
     if (sigma == 0.0) return mu;                        /* R7 */
+    /* the two uniforms of section 3.1 (i) and (ii) */
+    uint32_t ci[4] = {k, i, elt_id, 0}, cc[4] = {k, i, 0, 1};
+    if (keying == 1) {
+        ci[2] = program; ci[3] = 2;
+        cc[0] = event; cc[1] = 0; cc[2] = 0; cc[3] = 3;
+    }
     double z, zc;
     if (s_c == 0.0) {
-        double u = draw_u(k, i, elt_id, 0, seed);
+        double u = draw_u(ci[0], ci[1], ci[2], ci[3], seed);
         z = u; zc = 1.0 - u;
     } else if (s_i == 0.0) {
-        double u = draw_u(k, i, 0, 1, seed);
+        double u = draw_u(cc[0], cc[1], cc[2], cc[3], seed);
         z = u; zc = 1.0 - u;
     } else {
-        double u_pe = draw_u(k, i, elt_id, 0, seed);
-        double u_e = draw_u(k, i, 0, 1, seed);
+        double u_pe = draw_u(ci[0], ci[1], ci[2], ci[3], seed);
+        double u_e = draw_u(cc[0], cc[1], cc[2], cc[3], seed);
         combine_sigma(u_pe, u_e, s_i, s_c, &z, &zc);
     }
     double alpha, beta;
     orc_beta_fit(mu, sigma, max_l, &alpha, &beta);
     double x = orc_betaincinv_pair(alpha, beta, z, zc, NULL);
     return max_l * x;
+}
+
+double orc_su_loss(double mu, double s_i, double s_c, double max_l,
+                   uint32_t k, uint32_t i, uint32_t elt_id, uint64_t seed)
+{
+    return orc_su_loss_keyed(mu, s_i, s_c, max_l, k, i, elt_id, 0, 0, 0, seed);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -334,7 +354,8 @@ static double clamp_terms(double x, double retention, double limit)
  *   ELTs e = 0..n_elt-1: elt_layer[e] (layer it belongs to; ELTs of a layer
  *   are listed in their order), elt_id[e], elt_row_off[n_elt+1] into the row
  *   arrays, elt_terms[3e..3e+2] = (retention, limit, share).
- *   layer_terms[4l..4l+3] = (OccR, OccL, AggR, AggL).
+ *   layer_terms[4l..4l+3] = (OccR, OccL, AggR, AggL); layer_program[l] (may
+ *   be NULL: all 0) keys z_(Prog,E) when keying = 1 (R10).
  * Outputs (each may be NULL except ylt): ylt[l*n_trials + t] trial loss of
  *   layer l; ylt_pf[t] = sum over layers; gross[l*n_trials+t] = sum_k X_k;
  *   hits / hit_chk[l*n_trials+t]: number of non-zero lookups and the checksum
@@ -350,7 +371,7 @@ int orc_ara_run(int64_t n_trials, int64_t trial_base, const int64_t *offsets,
                 const int32_t *row_event, const float *row_mean,
                 const float *row_sigma_i, const float *row_sigma_c,
                 const float *row_max, uint64_t seed, int32_t su_enabled,
-                int32_t n_threads,
+                int32_t keying, const uint32_t *layer_program, int32_t n_threads,
                 double *ylt, double *ylt_pf, double *gross, int64_t *hits,
                 uint64_t *hit_chk, double *occ_view)
 {
@@ -401,8 +422,10 @@ int orc_ara_run(int64_t n_trials, int64_t trial_base, const int64_t *offsets,
                     double mu = row_mean[r];
                     double loss;
                     if (!su_enabled) loss = mu;
-                    else loss = orc_su_loss(mu, row_sigma_i[r], row_sigma_c[r],
-                                            row_max[r], k, i_abs, elt_id[e], seed);
+                    else loss = orc_su_loss_keyed(mu, row_sigma_i[r], row_sigma_c[r],
+                                                  row_max[r], k, i_abs, elt_id[e],
+                                                  layer_program ? layer_program[l] : 0u,
+                                                  (uint32_t)E, keying, seed);
                     double lp = elt_terms[3 * e + 2] *
                                 clamp_terms(loss, elt_terms[3 * e + 0], elt_terms[3 * e + 1]);
                     X += lp;                                          /* accumulate */

@@ -69,7 +69,10 @@ class ara_layer_desc(C.Structure):
 
 class ara_portfolio_desc(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("layers", C.POINTER(ara_layer_desc)),
-                ("seed", C.c_uint64), ("su_enabled", C.c_int32)]
+                ("seed", C.c_uint64), ("su_enabled", C.c_int32), ("keying", C.c_int32)]
+
+
+ARA_KEYING_OCCURRENCE, ARA_KEYING_PAPER = 0, 1
 
 
 ARA_BATCH_PORTFOLIO_MAJOR, ARA_BATCH_TRIAL_MAJOR = 0, 1
@@ -438,7 +441,8 @@ class _Desc:
         self.desc = ara_portfolio_desc(n_layers=len(pf.layers),
                                        layers=C.cast(layers, C.POINTER(ara_layer_desc)),
                                        seed=int(pf.seed) & 0xFFFFFFFFFFFFFFFF,
-                                       su_enabled=1 if pf.su_enabled else 0)
+                                       su_enabled=1 if pf.su_enabled else 0,
+                                       keying=int(getattr(pf, "keying", 0)))
 
 
 class DeviceYET:

@@ -76,6 +76,8 @@ struct Layout {
 ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, Layout *L) {
     if (!d || n_cat <= 0 || d->n_layers < 0 || (d->n_layers > 0 && !d->layers))
         return fail(ctx, ARA_E_INVALID_ARG, "bad portfolio description or catalogue size");
+    if (d->keying != ARA_KEYING_OCCURRENCE && d->keying != ARA_KEYING_PAPER)
+        return fail(ctx, ARA_E_INVALID_ARG, "unknown keying %d", d->keying);
     int64_t rows = 0;
     int32_t ne = 0, mx = 0;
     for (int l = 0; l < d->n_layers; ++l) {
@@ -326,6 +328,8 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
         D.evoff_base = (int64_t)l * ((int64_t)n_catalogue + 1);
         D.otab_base = desc->su_enabled ? -1 : (int64_t)l * n_catalogue;
         D.flags = 0;
+        D.program_id = ld.program_id;
+        D.keying = desc->keying;
         for (int j = 0; j < ld.n_elts; ++j, ++ei) {
             const ara_elt_desc &e = ld.elts[j];
             he[ei].elt_id = e.elt_id;

@@ -33,6 +33,8 @@ struct LayerDev {
     uint32_t flags;                      // OR of the row flags of the layer
     int32_t n_rows;
     int32_t nnz;                         // non-zero entries of otab (PU)
+    uint32_t program_id;                 // keys z_(Prog,E) under ARA_KEYING_PAPER
+    int32_t keying;                      // ARA_KEYING_* of the portfolio
     int32_t pad;
 };
 

@@ -532,10 +532,19 @@ struct SuArgs {
 
 // The draws of a hit as 24-bit grid integers: jI keyed (k, i, elt_id, 0),
 // jC keyed (k, i, 0, 1); only those the row's flags need are drawn.
-__device__ __forceinline__ void draw_j(uint32_t flags, uint32_t k, uint32_t i, uint32_t elt_id,
+// The two uniforms of a hit on the 2^-24 grid (j such that u = j 2^-24):
+// jI for the independent part, jC for the correlated part, drawn only when
+// the row needs them.  Occurrence keying: (k, i, elt_id, 0) and (k, i, 0, 1);
+// paper keying (section 3.1's z_(Prog,E) and z_(E)): (k, i, program, 2) and
+// (E, 0, 0, 3).
+__device__ __forceinline__ void draw_j(uint32_t flags, int32_t keying, uint32_t k, uint32_t i,
+                                       uint32_t elt_id, uint32_t program, uint32_t event,
                                        const PhiloxKeys &keys, uint32_t *jI, uint32_t *jC) {
-    *jI = (flags & ROW_CONLY) ? 0u : u24(philox10_x0(make_uint4(k, i, elt_id, 0u), keys));
-    *jC = (flags & (ROW_CONLY | ROW_CORR)) ? u24(philox10_x0(make_uint4(k, i, 0u, 1u), keys)) : 0u;
+    const bool paper = keying == ARA_KEYING_PAPER;
+    const uint4 cI = paper ? make_uint4(k, i, program, 2u) : make_uint4(k, i, elt_id, 0u);
+    const uint4 cC = paper ? make_uint4(event, 0u, 0u, 3u) : make_uint4(k, i, 0u, 1u);
+    *jI = (flags & ROW_CONLY) ? 0u : u24(philox10_x0(cI, keys));
+    *jC = (flags & (ROW_CONLY | ROW_CORR)) ? u24(philox10_x0(cC, keys)) : 0u;
 }
 
 // z and 1 - z of a hit (section 3.2).  A pure independent or correlated draw
@@ -616,7 +625,10 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         defer = true;
                     } else {
                         uint32_t jI, jC;
-                        draw_j(meta, (uint32_t)(seg + kl), i_abs, ed.elt_id, keys, &jI, &jC);
+                        const uint32_t ev =
+                            L.keying == ARA_KEYING_PAPER ? (uint32_t)A.ev[o0 + seg + kl] : 0u;
+                        draw_j(meta, L.keying, (uint32_t)(seg + kl), i_abs, ed.elt_id,
+                               L.program_id, ev, keys, &jI, &jC);
                         float z, zc;
                         if (REDO) {
                             hit_z<float>(meta, jI, jC, A.row_cfrac[row], &z, &zc);

@@ -196,11 +196,17 @@ def _mp_u(word):
     return mp.mpf(int((int(word) >> 8) | 1)) / mp.mpf(2) ** 24
 
 
-@pytest.mark.parametrize("corr", [False, True])
-def test_su_brute_force_mpmath(rocrand_philox, corr):
+@pytest.mark.parametrize("corr,keying", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_su_brute_force_mpmath(rocrand_philox, corr, keying):
     rng = np.random.default_rng(7 + corr)
     yet, pf = random_tiny_case(rng, n_cat=10, n_layers=2, max_elts=3, max_occ=5, n_trials=6,
                                dyadic=False, su=True, corr=corr)
+    pf.keying = keying
+    program = {}
+    for li, layer in enumerate(pf.layers):
+        layer.program_id = 11 + li
+        for e in layer.elts:
+            program[e.elt_id] = layer.program_id
     # keep every row away from the sigma cap so the mpmath root solve is tame
     for layer in pf.layers:
         for e in layer.elts:
@@ -219,12 +225,17 @@ def test_su_brute_force_mpmath(rocrand_philox, corr):
         if si + sc == 0.0:
             return Fraction(mu)
         mp.mp.dps = 40
-        if sc == 0.0:
-            z = _mp_u(word(k, i, elt.elt_id, 0))
-        elif si == 0.0:
-            z = _mp_u(word(k, i, 0, 1))
+        # section 3.1 (i) / (ii): the independent and the correlated uniform
+        if keying == 0:
+            cI, cC = (k, i, elt.elt_id, 0), (k, i, 0, 1)
         else:
-            u1, u2 = _mp_u(word(k, i, elt.elt_id, 0)), _mp_u(word(k, i, 0, 1))
+            cI, cC = (k, i, program[elt.elt_id], 2), (int(elt.event_ids[r]), 0, 0, 3)
+        if sc == 0.0:
+            z = _mp_u(word(*cI))
+        elif si == 0.0:
+            z = _mp_u(word(*cC))
+        else:
+            u1, u2 = _mp_u(word(*cI)), _mp_u(word(*cC))
             v1 = mp.sqrt(2) * mp.erfinv(2 * u1 - 1)
             v2 = mp.sqrt(2) * mp.erfinv(2 * u2 - 1)
             s = mp.mpf(si) + mp.mpf(sc)
@@ -452,6 +463,36 @@ def test_extreme_cases_short_circuit():
     assert np.array_equal(l2, 4.0 * O.betaincinv(a, b, uC))
     l3 = O.su_loss(1.0, 0.0, 0.0, 4.0, k, i, e, seed)          # sigma = 0: the mean
     assert np.all(l3 == 1.0)
+
+
+def test_paper_keying_draws(rocrand_philox):
+    """Section 3.1 keying: z_(Prog,E) is shared by every ELT of a program for
+    one occurrence and differs across programs; z_(E) is fixed per event.
+    With the Beta(1,1) moment fit the loss is max_l * z, so each hit's loss
+    shows its draw; the draws come from rocRAND's Philox."""
+    seed = 987654321
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], np.uint32)
+
+    def u(c):
+        w = int(rocrand_philox(np.array([c], np.uint32), key)[0, 0])
+        return ((w >> 8) | 1) * 2.0 ** -24
+
+    s1 = 4.0 * math.sqrt(1 / 12.0)          # (mu, sigma, max) = (2, s1, 4) fits Beta(1, 1)
+    for k, i, ev in [(0, 0, 3), (5, 17, 3), (2, 99, 41)]:
+        for prog in (0, 7, 8):
+            ref = 4.0 * u((k, i, prog, 2))
+            for elt in (1, 5, 900):
+                got = O.su_loss_keyed(2.0, s1, 0.0, 4.0, k, i, elt, prog, ev, 1, seed)
+                assert abs(got - ref) <= 1e-12 * ref
+        # the correlated-only draw depends on the event alone
+        refc = 4.0 * u((ev, 0, 0, 3))
+        for kk, ii, elt, prog in [(k, i, 1, 0), (k + 1, i + 3, 9, 4)]:
+            got = O.su_loss_keyed(2.0, 0.0, s1, 4.0, kk, ii, elt, prog, ev, 1, seed)
+            assert abs(got - refc) <= 1e-12 * refc
+    # the default keying ignores program and event
+    a = O.su_loss_keyed(2.0, s1, 0.0, 4.0, 3, 4, 5, 0, 0, 0, seed)
+    b = O.su_loss_keyed(2.0, s1, 0.0, 4.0, 3, 4, 5, 9, 77, 0, seed)
+    assert a == b and abs(a - 4.0 * u((3, 4, 5, 0))) <= 1e-12 * a
 
 
 def test_correlation_structure():

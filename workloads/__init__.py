@@ -116,6 +116,7 @@ class Portfolio:
     layers: List[Layer]
     seed: int = SEED_PHILOX
     su_enabled: bool = True
+    keying: int = 0                # 0: per-occurrence keys; 1: section 3.1's layout
 
     @property
     def n_elts(self) -> int:
@@ -256,12 +257,31 @@ def full_portfolio(su: bool = True, n_catalogue: int = 100_000) -> Portfolio:
 
 
 def config_full(n_trials: int = 1_000_000, with_times: bool = True, su: bool = True,
-                lam: float = 1000.0) -> Workload:
+                lam: float = 1000.0, n_catalogue: int = 100_000) -> Workload:
     """Full shape: 1,000,000 trials x Poisson(1000) over a 100,000-event
-    catalogue; one layer of 16 ELTs x 20,000 rows (dense FP32 tables)."""
-    yet = make_yet(n_trials, lam, 100_000, SEED_YET_FULL, with_times=with_times)
-    return Workload(name=f"ara_full_{n_trials}_trials_16_elts", yet=yet,
-                    portfolio=full_portfolio(su=su))
+    catalogue; one layer of 16 ELTs x 20,000 rows.  n_catalogue = 1,000,000
+    is the large-catalogue variant of the paper's direct-access example (16
+    ELTs of 20,000 non-zero rows over a 1,000,000-event catalogue)."""
+    yet = make_yet(n_trials, lam, n_catalogue, SEED_YET_FULL, with_times=with_times)
+    tag = "" if n_catalogue == 100_000 else f"_catalogue_{n_catalogue}"
+    return Workload(name=f"ara_full_{n_trials}_trials_16_elts{tag}", yet=yet,
+                    portfolio=full_portfolio(su=su, n_catalogue=n_catalogue))
+
+
+def sigma_capped(pf: Portfolio, fraction: float = 0.3, seed: int = 8) -> Portfolio:
+    """A copy of pf where a fraction of each ELT's rows have sigma_I = 3 mean
+    (with max = 4 mean that is sigma_beta = 0.75 > sigma_beta_max ~ 0.433, so
+    the fit hits the cap of section 3.3 and the shape is near-Bernoulli)."""
+    import copy
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed])))
+    out = copy.deepcopy(pf)
+    for layer in out.layers:
+        for e in layer.elts:
+            pick = rng.random(len(e.mean)) < fraction
+            si = np.array(e.sigma_i, np.float32, copy=True)
+            si[pick] = (np.float32(3.0) * np.asarray(e.mean, np.float32)[pick]).astype(np.float32)
+            e.sigma_i = si
+    return out
 
 
 def random_layer_terms(rng: np.random.Generator, lo: float = 1e5, hi: float = 1e9):
