@@ -64,8 +64,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sum-mode", default="naive32")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one 1 GiB device-to-device copy (a known-size kernel for "
-                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
+                    help="also run one elementwise kernel that reads and writes 1 GiB (a "
+                         "known-size kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--mode", choices=["step", "batched", "served", "precision"], default="step")
     ap.add_argument("--oracle-trials", type=int, default=3000, help="precision mode")
     ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
@@ -112,9 +112,11 @@ def main():
     stream = torch.cuda.current_stream()
     log("loaded YET and portfolio")
     if args.calibrate_copy:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB (a device copy
+        # would go to a DMA engine, which the counters do not see)
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 

@@ -108,17 +108,16 @@ __device__ __forceinline__ float log2_1m(float x, float w) {
 __device__ __forceinline__ void beta_cf32(float a, float b, float x, int n, int nmax, float *Nout,
                                           float *Dout) {
     float N = 1.0f, D = 1.0f;
-    const float apb = a + b;
-    for (int m = nmax >> 1; m >= 1; --m) {
-        const float fm = (float)m;
-        // even term 2m: p = m (b - m) x, q = (a + 2m - 1)(a + 2m)
-        const float te = a + (2.0f * fm - 1.0f);
-        const float qe = te * (te + 1.0f);
+    const float am1 = a - 1.0f, apbm1 = (a + b) - 1.0f;
+    float fm = (float)(nmax >> 1);           // exact small integer, stepped down exactly
+    for (int m = nmax >> 1; m >= 1; --m, fm -= 1.0f) {
+        // even term 2m: p = m (b - m) x, q = (a + 2m - 1)(a + 2m) = te (te + 1)
+        const float te = fmaf(2.0f, fm, am1);
+        const float qe = fmaf(te, te, te);
         const float pe = fm * (b - fm) * x;
-        // odd term 2m-1 (= 2(m-1)+1): p = -(a+m-1)(a+b+m-1) x, q = (a+2m-2)(a+2m-1)
-        const float to = te - 1.0f;
-        const float qo = to * te;
-        const float po = -(a + (fm - 1.0f)) * (apb + (fm - 1.0f)) * x;
+        // odd term 2m-1: p = -(a+m-1)(a+b+m-1) x, q = (a+2m-2)(a+2m-1) = (te - 1) te
+        const float qo = fmaf(te, te, -te);
+        const float po = -(am1 + fm) * (apbm1 + fm) * x;
         const bool on = 2 * m <= n;
         const float N1 = fmaf(qe, N, pe * D), D1 = qe * N;
         const float N2 = fmaf(qo, N1, po * D1), D2 = qo * N1;
@@ -171,15 +170,15 @@ __device__ __forceinline__ float beta_guess32(float a, float b, float z, float z
 }
 
 // I_x(a,b) (*I) and 1 - I_x(a,b) (*Ic), each on the side where it is
-// accurate, and the Beta density at x; lnb2 = log2 B(a, b); na / nb the
-// continued-fraction terms of the (a, b) and (b, a) branches; nmax the
-// wave-uniform bound of both.
+// accurate, and the prefactor x^a (1-x)^b / B(a,b) (*front; the density is
+// front / (x (1-x))); lnb2 = log2 B(a, b); na / nb the continued-fraction
+// terms of the (a, b) and (b, a) branches; nmax the wave-uniform bound of both.
 __device__ __forceinline__ void beta_inc32(float a, float b, float lnb2, int na, int nb, int nmax,
-                                           float x, float *I, float *Ic, float *dens) {
+                                           float x, float *I, float *Ic, float *front_out) {
     const float w = 1.0f - x;
     const float e2 = fmaf(a, __log2f(x), fmaf(b, log2_1m(x, w), -lnb2));
-    const float front = exp2f(e2);           // x^a (1-x)^b / B(a,b)
-    *dens = front * rcp_f(x * w);
+    const float front = exp2f(e2);
+    *front_out = front;
     const bool direct = x * (a + b + 2.0f) < a + 1.0f;
     // one loop for both branches: (a, b, x) directly, else (b, a, 1 - x)
     const float A = direct ? a : b, B = direct ? b : a, X = direct ? x : w;
@@ -194,11 +193,16 @@ __device__ __forceinline__ void beta_inc32(float a, float b, float lnb2, int na,
 // shapes inside the FP32 domain (kF32MinShape <= a, b <= kF32MaxShape).
 // Halley iterations on the side where the root is at most ~1/2 (mirroring
 // through I_{1-x}(b,a) = 1 - z otherwise), with the residual taken on the
-// side of the smaller of z, zc so it never cancels; the step sizes use
-// reciprocals (they only set the speed, the residual sets the root).  Stops
-// when every lane's last step was below 2^-10 of the root (Halley: the next
-// error ~ step^3).  Returns false in *ok if it did not converge (the caller
-// then uses the FP64 path).
+// side of the smaller of z, zc so it never cancels.  The first iteration
+// evaluates the continued fraction with about half its terms (the guess is
+// only good to ~1e-2, so a residual good to ~1e-4 serves that step); every
+// later one uses all of them.  The step sizes use reciprocals (they only set
+// the speed, the residual sets the root): with f the density and r the
+// residual, u = r / f = r x (1-x) / front and u (log f)' = r ((a-1)(1-x) -
+// (b-1) x) / front share one reciprocal.  Stops when every lane's last
+// full-accuracy step was below 2^-10 of the root (Halley: the next error ~
+// step^3).  Returns false in *ok if it did not converge (the caller then
+// uses the FP64 path).
 __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, int na, int nb,
                                                  float z, float zc, bool *ok) {
     float x0 = beta_guess32(a, b, z, zc);
@@ -217,20 +221,25 @@ __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, i
 #pragma unroll
     for (int bit = 32; bit >= 1; bit >>= 1)
         if (__any(nl >= (nmax | bit))) nmax |= bit;
+    const int nhalf = max(2, ((nmax >> 1) + 1) & ~1);
     float x = fminf(fmaxf(x0, 1e-30f), 0.75f);
     const bool lower = Z <= 0.5f;
+    const float am1 = A - 1.0f, bm1 = B - 1.0f;
     bool conv = false;
     for (int it = 0; it < 6; ++it) {
-        float I, Ic, dens;
-        beta_inc32(A, B, lnb2, NA, NB, nmax, x, &I, &Ic, &dens);
+        const int nt = it == 0 ? nhalf : nmax;
+        float I, Ic, front;
+        beta_inc32(A, B, lnb2, min(NA, nt), min(NB, nt), nt, x, &I, &Ic, &front);
         const float r = lower ? (I - Z) : (ZC - Ic);
-        const float u = r * rcp_f(dens);
-        const float hh = (A - 1.0f) * rcp_f(x) - (B - 1.0f) * rcp_f(1.0f - x);
-        const float t = u * rcp_f(1.0f - 0.5f * fminf(1.0f, u * hh));
+        const float w = 1.0f - x;
+        const float rf = r * rcp_f(front);
+        const float u = rf * (x * w);
+        const float uh = rf * fmaf(am1, w, -bm1 * x);
+        const float t = u * rcp_f(1.0f - 0.5f * fminf(1.0f, uh));
         float xn = x - t;
         if (!(xn > 0.0f)) xn = 0.5f * x;
         if (!(xn < 1.0f)) xn = 0.5f * (x + 1.0f);
-        conv = fabsf(xn - x) <= 9.765625e-4f * xn;
+        conv = it > 0 && fabsf(xn - x) <= 9.765625e-4f * xn;
         x = xn;
         if (__all(conv)) break;
     }
