@@ -500,8 +500,12 @@ __global__ __launch_bounds__(256) void k_ara_pu(PuArgs P) {
 // ---------------------------------------------------------------------------
 // secondary uncertainty
 // ---------------------------------------------------------------------------
-constexpr int kSeg = 1024;        // occurrences per LDS segment
-constexpr int kQCap = 512;        // hit queue (power of two)
+// LDS per wavefront: X[kSeg] floats + Q[kQCap] pairs = 4 KB, so LDS allows 40
+// waves per CU and the register budget sets the occupancy (7 per SIMD,
+// measured best on the full-shape workload against 5, 6 and 8)
+constexpr int kSeg = 512;         // occurrences per LDS segment
+constexpr int kQCap = 256;        // hit queue (power of two)
+#define ARA_SU_OCCUPANCY __attribute__((amdgpu_waves_per_eu(7, 7)))
 constexpr int kQMask = kQCap - 1;
 constexpr int kPerLane = (kQCap - kWave) / kWave;   // hits a lane appends per sub-step
 
@@ -747,7 +751,7 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
 
 // Main pass: one wavefront (block) per trial.
 template <int MODE, bool F64OUT, bool DIAG>
-__global__ __launch_bounds__(64) void k_ara_su(SuArgs A, PhiloxKeys keys) {
+__global__ __launch_bounds__(64) ARA_SU_OCCUPANCY void k_ara_su(SuArgs A, PhiloxKeys keys) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
     const int64_t t = blockIdx.x;
