@@ -42,9 +42,28 @@ PEAK_HBM_GBS = 8000.0
 # 157.3 TFLOP/s counts an FMA as two flops, i.e. 256 CUs x 128 lanes x 2.4 GHz
 # = 78.6e12 lane operations per second.
 PEAK_VALU_TOPS = 157.3 / 2.0
-# VALU lane operations per secondary-uncertainty draw of the main kernel at the
-# full-shape workload: SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/).
+# VALU lane operations per performed draw of the main SU kernel at the
+# full-shape workload: SQ_INSTS_VALU x 64 / performed draws, from rocprofv3
+# (profiles/ara_su_full_counters.md).  A draw is performed for a non-zero
+# lookup whose row can pay (its largest possible loss exceeds the ELT
+# retention, limit and share non-zero); the other non-zero lookups add
+# exactly 0 and are skipped.
 VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "659"))
+
+
+def live_draws(yet, pf):
+    """Non-zero lookups whose row can pay: the draws the SU kernel performs."""
+    n_cat = yet.n_catalogue
+    live = np.zeros(n_cat, np.int64)
+    for layer in pf.layers:
+        for e in layer.elts:
+            det = (np.asarray(e.sigma_i, np.float64) + np.asarray(e.sigma_c, np.float64)) == 0.0
+            scale = np.where(det, np.asarray(e.mean, np.float32), np.asarray(e.max_loss, np.float32))
+            ok = (scale > np.float32(e.retention)) & (np.float32(e.limit) != 0) & \
+                 (np.float32(e.share) != 0)
+            np.add.at(live, np.asarray(e.event_ids)[ok], 1)
+    occ = np.bincount(yet.event_ids, minlength=n_cat)
+    return int((occ.astype(np.int64) * live).sum())
 
 
 def log(*a):
@@ -147,8 +166,9 @@ def main():
     run_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
     log(f"SU: {ms_step:.3f} ms/step, ara_run {run_ms:.3f} ms; PML {pml} TVaR {tvar}")
 
-    # draws of the run (non-zero lookups): the unit of the SU kernel's work
+    # non-zero lookups of the run, and the draws performed (the SU kernel's unit of work)
     hits = ara.run(y, p, diagnostics=True, out_pf=out_p)["hits"].sum().item()
+    draws = live_draws(yet, pf)
     result = {
         "metric": "trial*event*ELT evaluations/s (1M-trial YET, secondary uncertainty)",
         "value": evals / (ms_step / 1e3),
@@ -166,11 +186,12 @@ def main():
                    "catalogue": yet.n_catalogue, "layers": 1, "elts": 16,
                    "rows_per_elt": 20000, "secondary_uncertainty": True,
                    "sum_mode": args.sum_mode, "return_periods": rps,
-                   "evaluations_per_step": evals, "draws_per_step": int(hits)},
+                   "evaluations_per_step": evals, "nonzero_lookups_per_step": int(hits),
+                   "draws_per_step": int(draws)},
         "pml": [float(v) for v in pml],
         "tvar": [float(v) for v in tvar],
     }
-    ops = VALU_OPS_PER_DRAW * hits
+    ops = VALU_OPS_PER_DRAW * draws
     result["roofline"] = {
         "kernel": "k_ara_su (+ k_ara_su_redo), ara_run",
         "bound": "alu",
@@ -180,7 +201,7 @@ def main():
         "frac": (ops / (run_ms / 1e3) / 1e12 / PEAK_VALU_TOPS) if ops else None,
         "traffic": None,
         "launch_ms": run_ms,
-        "draws_per_s": hits / (run_ms / 1e3),
+        "draws_per_s": draws / (run_ms / 1e3),
         "valu_ops_per_draw": VALU_OPS_PER_DRAW or None,
     }
 

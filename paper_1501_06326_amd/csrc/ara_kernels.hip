@@ -279,7 +279,8 @@ __device__ void fit_row(const RawRow &r, int32_t su, RowQ *q, uint32_t *flags, f
 __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restrict__ raw,
                           const int64_t *__restrict__ elt_row_off, const EltDev *__restrict__ elts,
                           LayerDev *__restrict__ layer, int32_t n_cat, int32_t su,
-                          const uint32_t *__restrict__ evoff, RowQ *__restrict__ rowq,
+                          const uint32_t *__restrict__ evoff, uint32_t *__restrict__ live_out,
+                          RowQ *__restrict__ rowq,
                           float *__restrict__ row_mean, float *__restrict__ row_cfrac,
                           uint32_t *__restrict__ row_meta, double *__restrict__ row_lnb,
                           float *__restrict__ otab) {
@@ -287,26 +288,38 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
     uint32_t fl_or = 0;
     for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_cat; e += gridDim.x * blockDim.x) {
         int64_t pos = L.row_base + evoff[e];
+        uint32_t live = 0;
         float X = 0.0f;
-        for (int j = 0; j < L.n_elts; ++j) {
-            const int32_t r = dat[(int64_t)j * n_cat + e];
-            if (r < 0) continue;
-            const RawRow rr = raw[elt_row_off[L.elt_begin] + r];
-            RowQ q;
-            uint32_t f;
-            float cf;
-            double lb;
-            fit_row(rr, su, &q, &f, &cf, &lb);
-            row_lnb[pos] = lb;
-            rowq[pos] = q;
-            row_mean[pos] = rr.mean;
-            row_cfrac[pos] = cf;
-            row_meta[pos] = f | (uint32_t)j;
-            fl_or |= f & ROW_FLAGS;
-            ++pos;
-            const EltDev ed = elts[L.elt_begin + j];
-            X += ed.share * clampf_terms(rr.mean, ed.retention, ed.limit);
-        }
+        // rows that can pay first, then the rows whose ELT terms give 0 for
+        // every draw (a loss never exceeds its scale: max_l, or the mean when
+        // there is no draw; scale <= retention, a zero limit or a zero share
+        // make share * min(max(loss - R, 0), L) exactly 0)
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < L.n_elts; ++j) {
+                const int32_t r = dat[(int64_t)j * n_cat + e];
+                if (r < 0) continue;
+                const RawRow rr = raw[elt_row_off[L.elt_begin] + r];
+                const EltDev ed = elts[L.elt_begin + j];
+                const bool det = !su || (double)rr.sigma_i + (double)rr.sigma_c == 0.0;
+                const float scale = det ? rr.mean : rr.max_loss;
+                const bool dead = scale <= ed.retention || ed.limit == 0.0f || ed.share == 0.0f;
+                if (dead != (pass == 1)) continue;
+                RowQ q;
+                uint32_t f;
+                float cf;
+                double lb;
+                fit_row(rr, su, &q, &f, &cf, &lb);
+                row_lnb[pos] = lb;
+                rowq[pos] = q;
+                row_mean[pos] = rr.mean;
+                row_cfrac[pos] = cf;
+                row_meta[pos] = f | (uint32_t)j;
+                fl_or |= f & ROW_FLAGS;
+                ++pos;
+                live += dead ? 0u : 1u;
+                X += ed.share * clampf_terms(rr.mean, ed.retention, ed.limit);
+            }
+        live_out[e] = live;
         if (otab) otab[L.otab_base + e] = clampf_terms(X, L.occ_r, L.occ_l);
     }
     if (fl_or) atomicOr(&layer->flags, fl_or);
@@ -506,6 +519,10 @@ __global__ __launch_bounds__(256) void k_ara_pu(PuArgs P) {
 constexpr int kSeg = 512;         // occurrences per LDS segment
 constexpr int kQCap = 256;        // hit queue (power of two)
 #define ARA_SU_OCCUPANCY __attribute__((amdgpu_waves_per_eu(7, 7)))
+// A layer's ELT records are staged in LDS when it has at most this many ELTs
+// (1 KB more per wavefront, still within the occupancy above); the draw then
+// needs one global load (the row) before its Philox key is known.
+constexpr int kEltLds = 64;
 constexpr int kQMask = kQCap - 1;
 constexpr int kPerLane = (kQCap - kWave) / kWave;   // hits a lane appends per sub-step
 
@@ -583,7 +600,7 @@ __device__ __forceinline__ void hit_z(uint32_t meta, uint32_t jI, uint32_t jC, T
 // such hits take the FP64 path in place.  Returns true when abandoned.
 template <int MODE, bool F64OUT, bool DIAG, bool REDO>
 __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys, int64_t t,
-                                         float *X, uint2 *Q) {
+                                         float *X, uint2 *Q, EltDev *El) {
     const int lane = threadIdx.x;
     const int64_t ti = A.trial_begin + t;
     const uint32_t i_abs = (uint32_t)ti;
@@ -595,6 +612,12 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
         const LayerDev L = A.layers[l];
         const uint32_t *eo = A.evoff + L.evoff_base;
         const int64_t rb0 = L.row_base;
+        const bool elt_lds = L.n_elts <= kEltLds;
+        if (elt_lds) {
+            __syncthreads();
+            for (int i = lane; i < L.n_elts; i += kWave) El[i] = A.elts[L.elt_begin + i];
+            __syncthreads();
+        }
         Acc<MODE> acc;
         uint64_t chk = 0;
         int64_t nh = 0;
@@ -617,11 +640,14 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                 if (lane < cnt) {
                     const uint2 e = Q[(h + lane) & kQMask];
                     const uint32_t kl = e.x, row = e.y;
+                    // the row's flags and Beta parameters in flight together
                     const uint32_t meta = A.row_meta[row];
-                    const EltDev ed = A.elts[L.elt_begin + (meta & 0xffffu)];
+                    const RowQ q = A.rowq[row];
+                    const uint32_t ei = meta & 0xffffu;
+                    const EltDev ed = elt_lds ? El[ei] : A.elts[L.elt_begin + ei];
                     float loss = 0.0f;
                     if (meta & ROW_DET) {
-                        loss = A.rowq[row].scale;
+                        loss = q.scale;
                     } else if (!REDO && (meta & (ROW_F64 | ROW_CORR))) {
                         // shapes outside the FP32 domain and the two-normal mix
                         // (whose special functions would inflate this pass's
@@ -641,7 +667,6 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                             z = (float)j * 5.9604644775390625e-08f;
                             zc = (float)(16777216u - j) * 5.9604644775390625e-08f;
                         }
-                        const RowQ q = A.rowq[row];
                         bool need64 = (meta & ROW_F64) || fminf(z, zc) < A.tail_band;
                         if (!need64) {
                             bool ok;
@@ -681,9 +706,12 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                 const bool valid = kl < segn;
                 uint32_t rb = 0, cnt = 0;
                 if (valid) {
+                    // the fast pass enqueues only the rows that can pay (they
+                    // come first); the diagnostic pass visits every row so it
+                    // counts every non-zero lookup
                     const int32_t E = A.ev[o0 + seg + kl];
                     rb = eo[E];
-                    cnt = eo[E + 1] - rb;
+                    cnt = DIAG ? eo[E + 1] - rb : A.evoff[L.live_base + E];
                 }
                 uint32_t done = 0;
                 while (!abandon) {
@@ -754,9 +782,10 @@ template <int MODE, bool F64OUT, bool DIAG>
 __global__ __launch_bounds__(64) ARA_SU_OCCUPANCY void k_ara_su(SuArgs A, PhiloxKeys keys) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
     const int64_t t = blockIdx.x;
     if (t >= A.trial_count) return;
-    if (su_trial<MODE, F64OUT, DIAG, false>(A, keys, t, X, Q) && threadIdx.x == 0)
+    if (su_trial<MODE, F64OUT, DIAG, false>(A, keys, t, X, Q, El) && threadIdx.x == 0)
         A.redo[atomicAdd(A.redo_count, 1u)] = (int32_t)t;
 }
 
@@ -766,9 +795,10 @@ template <int MODE, bool F64OUT, bool DIAG>
 __global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
     const uint32_t n = *A.redo_count;
     for (uint32_t r = blockIdx.x; r < n; r += gridDim.x)
-        su_trial<MODE, F64OUT, DIAG, true>(A, keys, (int64_t)A.redo[r], X, Q);
+        su_trial<MODE, F64OUT, DIAG, true>(A, keys, (int64_t)A.redo[r], X, Q, El);
 }
 
 // ---------------------------------------------------------------------------
@@ -817,6 +847,7 @@ template <int MODE, bool F64OUT>
 __global__ __launch_bounds__(64) void k_ara_batch(BatchArgs B) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
     const int lane = threadIdx.x;
     const unsigned long long n_items = (unsigned long long)B.n_items;
     while (true) {
@@ -847,7 +878,7 @@ __global__ __launch_bounds__(64) void k_ara_batch(BatchArgs B) {
         const int64_t t0 = tile * B.tile;
         const int64_t t1 = (t0 + B.tile) < A.trial_count ? (t0 + B.tile) : A.trial_count;
         for (int64_t t = t0; t < t1; ++t)
-            if (su_trial<MODE, F64OUT, false, false>(A, keys, t, X, Q) && lane == 0)
+            if (su_trial<MODE, F64OUT, false, false>(A, keys, t, X, Q, El) && lane == 0)
                 B.redo[atomicAdd(B.redo_count, 1u)] = ((unsigned long long)p << 32) | (uint64_t)t;
     }
 }
@@ -856,13 +887,14 @@ template <int MODE, bool F64OUT>
 __global__ __launch_bounds__(64) void k_ara_batch_redo(BatchArgs B) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
     const uint32_t n = *B.redo_count;
     for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
         const unsigned long long e = B.redo[r];
         SuArgs A;
         PhiloxKeys keys;
         batch_view(B, (int)(e >> 32), A, keys);
-        su_trial<MODE, F64OUT, false, true>(A, keys, (int64_t)(e & 0xffffffffull), X, Q);
+        su_trial<MODE, F64OUT, false, true>(A, keys, (int64_t)(e & 0xffffffffull), X, Q, El);
     }
 }
 
@@ -963,8 +995,8 @@ hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, con
                        h_layer.n_elts, n_cat, eo);
     hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, eo, (int64_t)n_cat + 1);
     hipLaunchKernelGGL(k_ev_fill, dim3(grid_for(n_cat, 256)), dim3(256), 0, s, dat, raw,
-                       elt_row_off, elts, d_layer, n_cat, su, eo, rowq, row_mean, row_cfrac,
-                       row_meta, row_lnb, otab);
+                       elt_row_off, elts, d_layer, n_cat, su, eo, evoff + h_layer.live_base, rowq,
+                       row_mean, row_cfrac, row_meta, row_lnb, otab);
     return hipGetLastError();
 }
 
