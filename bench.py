@@ -48,7 +48,34 @@ PEAK_VALU_TOPS = 157.3 / 2.0
 # lookup whose row can pay (its largest possible loss exceeds the ELT
 # retention, limit and share non-zero); the other non-zero lookups add
 # exactly 0 and are skipped.
-VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "659"))
+VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "702"))
+
+# HBM-side traffic of one launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# of this workload (profiles/ara_su_full_counters.md), each scaled by what the
+# counter reads for an elementwise kernel that reads and writes 1 GiB (FETCH
+# 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
+# the counters were taken with; null otherwise.
+PROFILED_TRAFFIC = {
+    "sources_sha256": "8dc1ce11332167d570ef1c88aa487ea9a7dd693a7e5b0d5458136eeb1cb91234",
+    "su_main_bytes": 73.72e9 + 0.092e9,     # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.086e9 + 0.0255e9,         # k_ara_pu: fetch + write, 1M trials
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1501_06326_amd", "csrc")
+    for f in ("ara_kernels.hip", "ara_math.h", "ara_internal.h", "ara_kernels.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled(key):
+    if kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+        return None
+    return PROFILED_TRAFFIC[key]
 
 
 def live_draws(yet, pf):
@@ -199,7 +226,8 @@ def main():
         "peak": PEAK_VALU_TOPS,
         "unit": "TOP/s",
         "frac": (ops / (run_ms / 1e3) / 1e12 / PEAK_VALU_TOPS) if ops else None,
-        "traffic": None,
+        "traffic": profiled("su_main_bytes") if (args.trials == 1_000_000 and
+                                                  args.catalogue == 100_000) else None,
         "launch_ms": run_ms,
         "draws_per_s": draws / (run_ms / 1e3),
         "valu_ops_per_draw": VALU_OPS_PER_DRAW or None,
@@ -227,7 +255,9 @@ def main():
         result["pu_path"] = {
             "ms_per_run": pu_ms, "evaluations_per_s": evals / (pu_ms / 1e3),
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": gbs / PEAK_HBM_GBS, "traffic": None, "bytes": byts},
+                         "frac": gbs / PEAK_HBM_GBS,
+                         "traffic": profiled("pu_bytes") if args.catalogue == 100_000 else None,
+                         "bytes": byts},
         }
         log(f"PU: {pu_ms:.3f} ms/run, {gbs:.0f} GB/s")
 

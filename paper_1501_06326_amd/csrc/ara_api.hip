@@ -110,8 +110,11 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
     size_t o = 0;
     L->layers = o; o += align256(sizeof(LayerDev) * (nl ? nl : 1));
     L->elts = o; o += align256(sizeof(EltDev) * (ne ? ne : 1));
-    // per layer ev_off[n_cat + 1], then per layer live[n_cat]
-    L->evoff = o; o += align256(sizeof(uint32_t) * (size_t)nl * (2 * (size_t)n_cat + 1));
+    // per layer ev_off[n_cat + 1]; then, from an even index, per layer the
+    // pairs (ev_off[e], rows of e that can pay) [n_cat] (one 8-byte load per
+    // occurrence in the fast pass)
+    L->evoff = o;
+    o += align256(sizeof(uint32_t) * ((size_t)nl * ((size_t)n_cat + 1) + 1 + (size_t)nl * 2 * n_cat));
     L->rowq = o; o += align256(sizeof(RowQ) * (size_t)(rows ? rows : 1));
     L->row_mean = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
     L->row_cfrac = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
@@ -327,7 +330,8 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
         D.n_elts = ld.n_elts;
         D.row_base = ri;
         D.evoff_base = (int64_t)l * ((int64_t)n_catalogue + 1);
-        D.live_base = (int64_t)nl * ((int64_t)n_catalogue + 1) + (int64_t)l * n_catalogue;
+        D.live_base = (((int64_t)nl * ((int64_t)n_catalogue + 1) + 1) & ~(int64_t)1) +
+                      (int64_t)l * 2 * n_catalogue;
         D.otab_base = desc->su_enabled ? -1 : (int64_t)l * n_catalogue;
         D.flags = 0;
         D.program_id = ld.program_id;

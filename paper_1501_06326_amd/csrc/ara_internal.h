@@ -36,8 +36,8 @@ struct LayerDev {
     uint32_t program_id;                 // keys z_(Prog,E) under ARA_KEYING_PAPER
     int32_t keying;                      // ARA_KEYING_* of the portfolio
     int32_t pad;
-    int64_t live_base;                   // first entry of the layer's live[n_cat] in the
-                                         // ev_off array: rows of event E that can pay
+    int64_t live_base;                   // even index of the layer's (ev_off[E], rows of E
+                                         // that can pay) pairs in the ev_off array
 };
 
 // Per-ELT record: id (keys the draws) and ELT financial terms.

@@ -319,7 +319,8 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
                 live += dead ? 0u : 1u;
                 X += ed.share * clampf_terms(rr.mean, ed.retention, ed.limit);
             }
-        live_out[e] = live;
+        live_out[2 * e] = evoff[e];
+        live_out[2 * e + 1] = live;
         if (otab) otab[L.otab_base + e] = clampf_terms(X, L.occ_r, L.occ_l);
     }
     if (fl_or) atomicOr(&layer->flags, fl_or);
@@ -710,8 +711,14 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                     // come first); the diagnostic pass visits every row so it
                     // counts every non-zero lookup
                     const int32_t E = A.ev[o0 + seg + kl];
-                    rb = eo[E];
-                    cnt = DIAG ? eo[E + 1] - rb : A.evoff[L.live_base + E];
+                    if (DIAG) {
+                        rb = eo[E];
+                        cnt = eo[E + 1] - rb;
+                    } else {
+                        const uint2 pr = reinterpret_cast<const uint2 *>(A.evoff + L.live_base)[E];
+                        rb = pr.x;
+                        cnt = pr.y;
+                    }
                 }
                 uint32_t done = 0;
                 while (!abandon) {
