@@ -513,7 +513,7 @@ def bench_served(args):
                     dt = start + arr[i] - time.perf_counter()
                     if dt > 0:
                         time.sleep(dt)
-                    rid = srv.submit(r.portfolio, r.trial_begin, r.trial_count, rps)
+                    rid = srv.submit(r.portfolio, r.trial_begin, r.trial_count, rps, borrow=True)
                     with lock:
                         ids[rid] = i
 

@@ -219,13 +219,17 @@ ara_status ara_sync_status(ara_context *ctx, void *stream);
  * may be NULL), laid out as for ara_run over opts->trial_count trials.
  * opts->d_hits / d_hit_chk must be NULL; its d_scratch is not used (the batch
  * scratch is the explicit argument, ara_batch_scratch_size bytes).
- * cfg = NULL: trial_tile 4, 16 waves per CU, portfolio-major unless every
- * portfolio is primary-uncertainty. */
+ * The launch takes one of two forms: one workgroup per work item (the
+ * hardware dispatcher hands items out in order as wavefronts retire), or a
+ * persistent grid of waves_per_cu wavefronts per CU that take items from an
+ * atomic counter.  cfg = NULL: trial_tile 1, one workgroup per item,
+ * portfolio-major unless every portfolio is primary-uncertainty. */
 #define ARA_BATCH_PORTFOLIO_MAJOR 0
 #define ARA_BATCH_TRIAL_MAJOR 1
 typedef struct {
     int32_t trial_tile;         /* trials per work item (>= 1) */
-    int32_t waves_per_cu;       /* resident wavefronts per compute unit (>= 1) */
+    int32_t waves_per_cu;       /* 0: one workgroup per work item (at most 2^31 - 1 items);
+                                   > 0: persistent form, resident wavefronts per CU */
     int32_t order;              /* ARA_BATCH_PORTFOLIO_MAJOR or ARA_BATCH_TRIAL_MAJOR */
 } ara_batch_config;
 
@@ -237,9 +241,10 @@ ara_status ara_run_batch(ara_context *ctx, const ara_yet *yet, int32_t n_portfol
                          void *stream);
 
 /* Autotuner: times ara_run_batch over opts' trial range (HIP events, after
- * one warmup launch) for trial tiles {1, 2, 4} x {12, 16, 20} waves per CU x
- * both orders and returns the fastest configuration and its time.  A range
- * of a few thousand trials keeps it to seconds.  Synchronises. */
+ * one warmup launch) for trial tiles {1, 2, 4} x waves per CU {0 (one
+ * workgroup per item), 16, 20} x both orders and returns the fastest
+ * configuration and its time.  A range of a few thousand trials keeps it to
+ * seconds.  Synchronises. */
 ara_status ara_batch_autotune(ara_context *ctx, const ara_yet *yet, int32_t n_portfolios,
                               ara_portfolio *const *pfs, const ara_run_opts *opts,
                               void *const *d_ylt_layers, void *const *d_ylt_portfolio,
@@ -305,11 +310,17 @@ typedef struct {
 ara_status ara_server_create(int hip_device, int64_t n_trials, int32_t n_catalogue,
                              const int64_t *d_trial_offsets, const int32_t *d_event_ids,
                              const ara_server_config *cfg, ara_server **out);
-/* Copies the description; fails with ARA_E_WORKSPACE_TOO_SMALL when the
+/* flags: ARA_SUBMIT_WANT_YLT returns a host copy of the portfolio YLT with
+ * the result; ARA_SUBMIT_BORROW keeps pointers to the description's row
+ * arrays instead of copying them (the caller keeps them valid and unchanged
+ * until the request's result has been polled); without it the description is
+ * copied during the call.  Fails with ARA_E_WORKSPACE_TOO_SMALL when the
  * request alone can never fit the pool. */
+#define ARA_SUBMIT_WANT_YLT 1
+#define ARA_SUBMIT_BORROW 2
 ara_status ara_server_submit(ara_server *srv, const ara_portfolio_desc *desc, int64_t trial_begin,
                              int64_t trial_count, const double *return_periods, int32_t n_rp,
-                             int32_t want_ylt, uint64_t *request_id);
+                             int32_t flags, uint64_t *request_id);
 /* Up to max_results finished requests (waiting up to wait_s seconds for the
  * first one); *n_out receives the count. */
 ara_status ara_server_poll(ara_server *srv, ara_server_result *out, int32_t max_results,

@@ -360,12 +360,15 @@ def ara_server_create(device: int, n_trials: int, n_catalogue: int, d_offsets: i
     return h
 
 
+ARA_SUBMIT_WANT_YLT, ARA_SUBMIT_BORROW = 1, 2
+
+
 def ara_server_submit(srv, desc: "ara_portfolio_desc", trial_begin: int, trial_count: int,
-                      return_periods, want_ylt: bool) -> int:
+                      return_periods, flags: int) -> int:
     rp = np.ascontiguousarray(return_periods, np.float64)
     rid = C.c_uint64()
     rc = lib().ara_server_submit(srv, C.byref(desc), int(trial_begin), int(trial_count),
-                                 rp.ctypes.data, rp.shape[0], 1 if want_ylt else 0, C.byref(rid))
+                                 rp.ctypes.data, rp.shape[0], int(flags), C.byref(rid))
     if rc != ARA_OK:
         raise AraError(rc, "ara_server_submit: " + ara_status_string(rc))
     return int(rid.value)
@@ -720,14 +723,21 @@ class Server:
         cfg = ara_server_config(max_inflight=int(max_inflight), max_batch=int(max_batch),
                                 sum_mode=SUM_MODES[sum_mode], reserved=0,
                                 d_pool=self.pool.data_ptr(), pool_bytes=int(pool_bytes))
+        self._lent = {}
         self.h = ara_server_create(device, int(self.off.shape[0] - 1), int(yet.n_catalogue),
                                    _ptr(self.off), _ptr(self.ev), cfg)
 
     def submit(self, pf, trial_begin: int, trial_count: int, return_periods=(100.0, 250.0),
-               want_ylt: bool = False) -> int:
-        d = _Desc(pf)     # the server copies the description during the call
-        return ara_server_submit(self.h, d.desc, trial_begin, trial_count, return_periods,
-                                 want_ylt)
+               want_ylt: bool = False, borrow: bool = False) -> int:
+        """Queue a request.  borrow=True lends the row arrays instead of having
+        the server copy them; they are kept alive here until the result is
+        polled."""
+        d = _Desc(pf)
+        flags = (ARA_SUBMIT_WANT_YLT if want_ylt else 0) | (ARA_SUBMIT_BORROW if borrow else 0)
+        rid = ara_server_submit(self.h, d.desc, trial_begin, trial_count, return_periods, flags)
+        if borrow:
+            self._lent[rid] = d
+        return rid
 
     def poll(self, max_results: int = 64, wait_s: float = 0.0):
         res = []
@@ -738,13 +748,15 @@ class Server:
             if r.ylt_count > 0 and bool(r.ylt):
                 item["ylt"] = np.ctypeslib.as_array(r.ylt, shape=(int(r.ylt_count),)).copy()
             ara_server_release(self.h, r.request_id)
+            self._lent.pop(int(r.request_id), None)
             res.append(item)
         return res
 
     def close(self):
         if self.h is not None:
-            ara_server_destroy(self.h)
+            ara_server_destroy(self.h)      # waits for the queued requests
             self.h = None
+            self._lent.clear()
 
     def __enter__(self):
         return self

@@ -677,14 +677,14 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
         return fail(ctx, ARA_E_UNSUPPORTED,
                     "ara_run_batch: hit diagnostics and the occurrence view are per-portfolio only");
     if (!(o.tail_band > 0.0f)) o.tail_band = kDefaultTailBand;
-    ara_batch_config c = {4, 16, ARA_BATCH_TRIAL_MAJOR};
+    ara_batch_config c = {1, 0, ARA_BATCH_TRIAL_MAJOR};
     if (cfg) {
         c = *cfg;
     } else {
         for (int32_t i = 0; i < n; ++i)
             if (pfs && pfs[i] && pfs[i]->su_enabled) c.order = ARA_BATCH_PORTFOLIO_MAJOR;
     }
-    if (c.trial_tile < 1 || c.waves_per_cu < 1 ||
+    if (c.trial_tile < 1 || c.waves_per_cu < 0 ||
         (c.order != ARA_BATCH_PORTFOLIO_MAJOR && c.order != ARA_BATCH_TRIAL_MAJOR))
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad batch configuration");
     if (ranges && c.order == ARA_BATCH_TRIAL_MAJOR)
@@ -745,7 +745,10 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     B.redo_count = (uint32_t *)(sc + 8);
     B.redo = (unsigned long long *)(sc + batch_redo_off(n));
     B.status = status ? status : ctx->d_status;
-    plan->grid = ctx->n_cu * c.waves_per_cu;
+    if (c.waves_per_cu == 0 && B.n_items > 0x7fffffffll)
+        return fail(ctx, ARA_E_UNSUPPORTED, "ara_run_batch: more than 2^31 work items for the "
+                                            "one-workgroup-per-item form; use waves_per_cu > 0");
+    plan->grid = ctx->n_cu * c.waves_per_cu;           // 0: one workgroup per item
     plan->redo_grid = ctx->n_cu * 4;
     plan->mode = o.sum_mode;
     plan->f64out = o.ylt_dtype == ARA_F64;
@@ -797,10 +800,10 @@ ara_status ara_batch_autotune(ara_context *ctx, const ara_yet *yet, int32_t n_po
     ARA_HIP(ctx, hipEventCreate(&e0));
     ARA_HIP(ctx, hipEventCreate(&e1));
     const int tiles[] = {1, 2, 4};
-    const int waves[] = {12, 16, 20};
+    const int waves[] = {0, 16, 20};                   // 0: one workgroup per item
     const int orders[] = {ARA_BATCH_PORTFOLIO_MAJOR, ARA_BATCH_TRIAL_MAJOR};
     double bms = 1e300;
-    ara_batch_config bc = {4, 16, ARA_BATCH_PORTFOLIO_MAJOR};
+    ara_batch_config bc = {1, 0, ARA_BATCH_PORTFOLIO_MAJOR};
     ara_status st = ARA_OK;
     bool warm = false;
     for (int oi = 0; oi < 2 && st == ARA_OK; ++oi)

@@ -850,44 +850,73 @@ __device__ __forceinline__ void batch_view(const BatchArgs &B, int p, SuArgs &A,
     keys.k1 = P.k1;
 }
 
+// One work item of a batch: a tile of B.tile trials of one portfolio.  The
+// item index is wave-uniform; the portfolio and tile are derived from it
+// (trial-major: tile-then-portfolio; portfolio-major: each portfolio's block
+// of items in turn).
+template <int MODE, bool F64OUT>
+__device__ __forceinline__ void batch_item(const BatchArgs &B, unsigned long long item, float *X,
+                                           uint2 *Q, EltDev *El) {
+    int64_t tile;
+    int p;
+    if (B.trial_major) {
+        tile = (int64_t)(item / (unsigned long long)B.n_pf);
+        p = (int)(item % (unsigned long long)B.n_pf);
+    } else {
+        // the portfolio whose block of work items holds this item
+        int lo_p = 0, hi_p = B.n_pf - 1;
+        while (lo_p < hi_p) {
+            const int mid = (lo_p + hi_p + 1) >> 1;
+            if ((unsigned long long)B.pfs[mid].tile_base <= item) lo_p = mid; else hi_p = mid - 1;
+        }
+        p = lo_p;
+        tile = (int64_t)item - B.pfs[p].tile_base;
+    }
+    // wave-uniform by construction; said explicitly so the portfolio's
+    // pointers are read with scalar loads into scalar registers
+    p = __builtin_amdgcn_readfirstlane(p);
+    tile = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(tile >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)tile));
+    SuArgs A;
+    PhiloxKeys keys;
+    batch_view(B, p, A, keys);
+    const int64_t t0 = tile * B.tile;
+    const int64_t t1 = (t0 + B.tile) < A.trial_count ? (t0 + B.tile) : A.trial_count;
+    for (int64_t t = t0; t < t1; ++t)
+        if (su_trial<MODE, F64OUT, false, false>(A, keys, t, X, Q, El) && threadIdx.x == 0)
+            B.redo[atomicAdd(B.redo_count, 1u)] = ((unsigned long long)p << 32) | (uint64_t)t;
+}
+
+// Persistent form: grid-wide loop over work items taken from an atomic
+// counter (waves_per_cu wavefronts per CU stay resident).
 template <int MODE, bool F64OUT>
 __global__ __launch_bounds__(64) void k_ara_batch(BatchArgs B) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
     __shared__ EltDev El[kEltLds];
-    const int lane = threadIdx.x;
     const unsigned long long n_items = (unsigned long long)B.n_items;
     while (true) {
         unsigned long long item = 0;
-        if (lane == 0) item = atomicAdd(B.counter, 1ull);
+        if (threadIdx.x == 0) item = atomicAdd(B.counter, 1ull);
         const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)item);
         const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(item >> 32));
         item = ((unsigned long long)hi << 32) | lo;
         if (item >= n_items) break;
-        int64_t tile;
-        int p;
-        if (B.trial_major) {
-            tile = (int64_t)(item / (unsigned long long)B.n_pf);
-            p = (int)(item % (unsigned long long)B.n_pf);
-        } else {
-            // the portfolio whose block of work items holds this item
-            int lo_p = 0, hi_p = B.n_pf - 1;
-            while (lo_p < hi_p) {
-                const int mid = (lo_p + hi_p + 1) >> 1;
-                if ((unsigned long long)B.pfs[mid].tile_base <= item) lo_p = mid; else hi_p = mid - 1;
-            }
-            p = lo_p;
-            tile = (int64_t)item - B.pfs[p].tile_base;
-        }
-        SuArgs A;
-        PhiloxKeys keys;
-        batch_view(B, p, A, keys);
-        const int64_t t0 = tile * B.tile;
-        const int64_t t1 = (t0 + B.tile) < A.trial_count ? (t0 + B.tile) : A.trial_count;
-        for (int64_t t = t0; t < t1; ++t)
-            if (su_trial<MODE, F64OUT, false, false>(A, keys, t, X, Q, El) && lane == 0)
-                B.redo[atomicAdd(B.redo_count, 1u)] = ((unsigned long long)p << 32) | (uint64_t)t;
+        batch_item<MODE, F64OUT>(B, item, X, Q, El);
     }
+}
+
+// One workgroup per work item: the dispatcher hands the items out in index
+// order as wavefronts retire, and a wavefront keeps no state across items,
+// so the kernel runs at the single-portfolio kernel's occupancy.
+template <int MODE, bool F64OUT>
+__global__ __launch_bounds__(64) ARA_SU_OCCUPANCY void k_ara_batch_items(BatchArgs B) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
+    const unsigned long long item = blockIdx.x;
+    if (item >= (unsigned long long)B.n_items) return;
+    batch_item<MODE, F64OUT>(B, item, X, Q, El);
 }
 
 template <int MODE, bool F64OUT>
@@ -1084,10 +1113,16 @@ hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s) {
     return f64out ? su_dispatch2<ARA_SUM_F64, true>(p, s) : su_dispatch2<ARA_SUM_F64, false>(p, s);
 }
 
+// grid <= 0: one workgroup per work item; otherwise the persistent form with
+// that many workgroups.
 template <int MODE, bool F64OUT>
 static void batch_dispatch(const BatchArgs &B, int grid, int redo_grid, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B.counter, B.redo_count);
-    hipLaunchKernelGGL((k_ara_batch<MODE, F64OUT>), dim3(grid), dim3(64), 0, s, B);
+    if (grid <= 0)
+        hipLaunchKernelGGL((k_ara_batch_items<MODE, F64OUT>), dim3((unsigned)B.n_items), dim3(64),
+                           0, s, B);
+    else
+        hipLaunchKernelGGL((k_ara_batch<MODE, F64OUT>), dim3(grid), dim3(64), 0, s, B);
     hipLaunchKernelGGL((k_ara_batch_redo<MODE, F64OUT>), dim3(redo_grid), dim3(64), 0, s, B);
 }
 

@@ -262,8 +262,9 @@ bool ara_server::launch(Slot &s) {
     std::memset(&o, 0, sizeof o);
     o.sum_mode = cfg.sum_mode;
     o.ylt_dtype = ARA_F32;
-    // one trial per work item and 20 waves per CU: small requests still fill the chip
-    const ara_batch_config bc = {1, 20, ARA_BATCH_PORTFOLIO_MAJOR};
+    // one trial per work item, one workgroup per item: small requests still
+    // fill the chip, at the single-portfolio kernel's occupancy
+    const ara_batch_config bc = {1, 0, ARA_BATCH_PORTFOLIO_MAJOR};
     ara_status st = ARA_OK;
     if (hipMemsetAsync(s.d_status, 0, sizeof(ara::Status), s.stream) != hipSuccess) st = ARA_E_HIP;
     if (st == ARA_OK)
@@ -435,8 +436,9 @@ ara_status ara_server_create(int hip_device, int64_t n_trials, int32_t n_catalog
 
 ara_status ara_server_submit(ara_server *srv, const ara_portfolio_desc *desc, int64_t trial_begin,
                              int64_t trial_count, const double *return_periods, int32_t n_rp,
-                             int32_t want_ylt, uint64_t *request_id) {
+                             int32_t flags, uint64_t *request_id) {
     if (!srv || !desc || !return_periods || n_rp <= 0 || n_rp > ARA_SERVER_MAX_RP ||
+        (flags & ~(ARA_SUBMIT_WANT_YLT | ARA_SUBMIT_BORROW)) ||
         trial_begin < 0 || trial_count <= 0 || trial_begin + trial_count > srv->n_trials ||
         desc->n_layers < 0 || (desc->n_layers > 0 && !desc->layers))
         return ARA_E_INVALID_ARG;
@@ -462,18 +464,21 @@ ara_status ara_server_submit(ara_server *srv, const ara_portfolio_desc *desc, in
         for (int j = 0; j < L.n_elts; ++j) {
             const ara_elt_desc &e = L.elts[j];
             const size_t n = (size_t)e.n_rows;
-            auto copyf = [&](std::vector<std::vector<float>> &dst, const float *src) -> const float * {
-                if (!src) return nullptr;
-                dst.emplace_back(src, src + n);
-                return dst.back().data();
-            };
-            ara_elt_desc c = e;
-            r->ev.emplace_back(e.event_ids, e.event_ids + n);
-            c.event_ids = r->ev.back().data();
-            c.mean = copyf(r->mean, e.mean);
-            c.sigma_i = copyf(r->si, e.sigma_i);
-            c.sigma_c = copyf(r->sc, e.sigma_c);
-            c.max_loss = copyf(r->mx, e.max_loss);
+            ara_elt_desc c = e;             // borrowed: the caller's row arrays
+            if (!(flags & ARA_SUBMIT_BORROW)) {
+                auto copyf = [&](std::vector<std::vector<float>> &dst,
+                                 const float *src) -> const float * {
+                    if (!src) return nullptr;
+                    dst.emplace_back(src, src + n);
+                    return dst.back().data();
+                };
+                r->ev.emplace_back(e.event_ids, e.event_ids + n);
+                c.event_ids = r->ev.back().data();
+                c.mean = copyf(r->mean, e.mean);
+                c.sigma_i = copyf(r->si, e.sigma_i);
+                c.sigma_c = copyf(r->sc, e.sigma_c);
+                c.max_loss = copyf(r->mx, e.max_loss);
+            }
             r->elts[l][j] = c;
         }
         r->layers[l].elts = r->elts[l].data();
@@ -484,7 +489,7 @@ ara_status ara_server_submit(ara_server *srv, const ara_portfolio_desc *desc, in
     r->trial_count = trial_count;
     r->rps.assign(return_periods, return_periods + n_rp);
     metric_ranks(r);
-    r->want_ylt = want_ylt;
+    r->want_ylt = (flags & ARA_SUBMIT_WANT_YLT) ? 1 : 0;
     ara_status st = request_footprint(srv, r);
     if (st != ARA_OK) {
         delete r;

@@ -55,11 +55,12 @@ REQS = [(0, 0, 5000), (1, 0, 5000), (2, 1000, 3000), (3, 0, 4999), (4, 17, 2500)
         (0, 2500, 2500), (2, 0, 5000), (3, 4000, 1000)]
 
 
-def serve(yet, pfs, reqs, together, **kw):
+def serve(yet, pfs, reqs, together, borrow=False, **kw):
     from paper_1501_06326_amd import Server
     with Server(yet, **kw) as srv:
         if together:
-            ids = [srv.submit(pfs[k], b, c, RPS, want_ylt=True) for k, b, c in reqs]
+            ids = [srv.submit(pfs[k], b, c, RPS, want_ylt=True, borrow=borrow)
+                   for k, b, c in reqs]
             got = collect(srv, ids)
         else:
             got = {}
@@ -77,6 +78,11 @@ def test_serve_mix_equals_alone(setup):
     alone = serve(yet, pfs, REQS, False, pool_bytes=256 << 20, max_inflight=3, max_batch=4)
     say("serve together")
     mix = serve(yet, pfs, REQS, True, pool_bytes=256 << 20, max_inflight=3, max_batch=4)
+    say("serve together, borrowed descriptions")
+    lent = serve(yet, pfs, REQS, True, borrow=True, pool_bytes=256 << 20, max_inflight=2,
+                 max_batch=3)
+    for r0, r1 in zip(alone, lent):
+        assert r1["status"] == 0 and np.array_equal(r0["ylt"], r1["ylt"])
     for r0, r1 in zip(alone, mix):
         assert r0["status"] == 0 and r1["status"] == 0
         assert np.array_equal(r0["ylt"], r1["ylt"])
