@@ -67,7 +67,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Byte layout of a portfolio workspace.
 struct Layout {
-    size_t layers, elts, evoff, rowq, row_mean, row_cfrac, row_meta, row_lnb, otab, sp_bits, sp_rank,
+    size_t layers, elts, evoff, liveoff, rowq, rowf, row_mean, row_cfrac, row_meta, row_lnb, otab,
+        sp_bits, sp_rank,
         sp_vals, raw, eltoff, dat, total;
     int64_t n_rows = 0;
     int32_t n_elts = 0, max_layer_elts = 0;
@@ -115,7 +116,9 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
     // occurrence in the fast pass)
     L->evoff = o;
     o += align256(sizeof(uint32_t) * ((size_t)nl * ((size_t)n_cat + 1) + 1 + (size_t)nl * 2 * n_cat));
+    L->liveoff = o; o += align256(sizeof(uint32_t) * (size_t)nl * ((size_t)n_cat + 1));
     L->rowq = o; o += align256(sizeof(RowQ) * (size_t)(rows ? rows : 1));
+    L->rowf = o; o += align256(sizeof(RowF) * (size_t)(rows ? rows : 1));
     L->row_mean = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
     L->row_cfrac = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
     L->row_meta = o; o += align256(sizeof(uint32_t) * (size_t)(rows ? rows : 1));
@@ -368,6 +371,7 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
     p->d_elts = (EltDev *)(w + L.elts);
     p->d_evoff = (uint32_t *)(w + L.evoff);
     p->d_rowq = (RowQ *)(w + L.rowq);
+    p->d_rowf = (RowF *)(w + L.rowf);
     p->d_row_mean = (float *)(w + L.row_mean);
     p->d_row_cfrac = (float *)(w + L.row_cfrac);
     p->d_row_meta = (uint32_t *)(w + L.row_meta);
@@ -413,7 +417,9 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
     const size_t nwc = ((size_t)n_catalogue + 31) / 32;
     for (int l = 0; l < nl; ++l) {
         ARA_HIP_P(launch_build_layer(d_raw, d_eltoff, p->d_elts, p->d_layers + l, hl[l], n_catalogue,
-                                     p->su_enabled, d_dat, p->d_evoff, p->d_rowq, p->d_row_mean,
+                                     p->su_enabled, d_dat, p->d_evoff,
+                                     (uint32_t *)(w + L.liveoff) + (size_t)l * ((size_t)n_catalogue + 1),
+                                     p->d_rowq, p->d_rowf, p->d_row_mean,
                                      p->d_row_cfrac, p->d_row_meta, p->d_row_lnb, p->d_otab,
                                      ctx->d_status, s));
         if (!p->su_enabled)
@@ -529,6 +535,7 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
     p.elts = pf->d_elts;
     p.evoff = pf->d_evoff;
     p.rowq = pf->d_rowq;
+    p.rowf = pf->d_rowf;
     p.row_mean = pf->d_row_mean;
     p.row_cfrac = pf->d_row_cfrac;
     p.row_meta = pf->d_row_meta;
@@ -707,6 +714,7 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
         b.elts = p->d_elts;
         b.evoff = p->d_evoff;
         b.rowq = p->d_rowq;
+        b.rowf = p->d_rowf;
         b.row_mean = p->d_row_mean;
         b.row_cfrac = p->d_row_cfrac;
         b.row_meta = p->d_row_meta;

@@ -53,6 +53,17 @@ struct RowQ {
     float scale, a, b, lnb;
 };
 
+// Compact record of a row that can pay, read by the fast passes with one
+// 32-byte load (one cache line): the layer's such rows are contiguous,
+// event-major.  row is the index of the same row in the per-row arrays.
+struct __attribute__((aligned(16))) RowF {
+    float scale, a, b, lnb;
+    uint32_t meta;
+    float cfrac;
+    uint32_t row;
+    uint32_t pad;
+};
+
 // Raw host rows staged on the device for the build kernels.
 struct RawRow {
     int32_t event;
@@ -101,6 +112,7 @@ struct ara_portfolio {
     ara::EltDev *d_elts;
     uint32_t *d_evoff;
     ara::RowQ *d_rowq;
+    ara::RowF *d_rowf;
     float *d_row_mean;
     float *d_row_cfrac;
     uint32_t *d_row_meta;

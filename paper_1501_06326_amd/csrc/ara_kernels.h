@@ -38,6 +38,7 @@ struct SuLaunch {
     const EltDev *elts;
     const uint32_t *evoff;
     const RowQ *rowq;
+    const RowF *rowf;
     const float *row_mean;
     const float *row_cfrac;
     const uint32_t *row_meta;
@@ -62,6 +63,7 @@ struct BatchPf {
     const EltDev *elts;
     const uint32_t *evoff;
     const RowQ *rowq;
+    const RowF *rowf;
     const float *row_mean;
     const float *row_cfrac;
     const uint32_t *row_meta;
@@ -99,7 +101,8 @@ hipError_t launch_check_rows(const RawRow *raw, int64_t n, int32_t n_cat, int32_
                              hipStream_t s);
 hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, const EltDev *elts,
                               LayerDev *d_layer, const LayerDev &h_layer, int32_t n_cat, int32_t su,
-                              int32_t *dat, uint32_t *evoff, RowQ *rowq, float *row_mean,
+                              int32_t *dat, uint32_t *evoff, uint32_t *liveoff, RowQ *rowq,
+                              RowF *rowf, float *row_mean,
                               float *row_cfrac, uint32_t *row_meta, double *row_lnb, float *otab,
                               Status *st, hipStream_t s);
 hipError_t launch_pu(const PuLaunch &p, int mode, bool f64out, hipStream_t s);

@@ -191,13 +191,33 @@ __global__ void k_dat_scatter(const RawRow *__restrict__ raw, const int64_t *__r
     }
 }
 
-__global__ void k_ev_count(const int32_t *__restrict__ dat, int32_t n_elts, int32_t n_cat,
-                           uint32_t *__restrict__ evoff) {
+// A row whose ELT terms give 0 for every draw: a loss never exceeds its
+// scale (max_l, or the mean when there is no draw), so scale <= retention,
+// a zero limit or a zero share make share * min(max(loss - R, 0), L)
+// exactly 0.
+__device__ __forceinline__ bool row_cannot_pay(const RawRow &rr, const EltDev &ed, int32_t su) {
+    const bool det = !su || (double)rr.sigma_i + (double)rr.sigma_c == 0.0;
+    const float scale = det ? rr.mean : rr.max_loss;
+    return scale <= ed.retention || ed.limit == 0.0f || ed.share == 0.0f;
+}
+
+// Rows per catalogue event in the layer (evoff) and rows that can pay (liveoff).
+__global__ void k_ev_count(const int32_t *__restrict__ dat, const RawRow *__restrict__ raw,
+                           const int64_t *__restrict__ elt_row_off, const EltDev *__restrict__ elts,
+                           int32_t elt_begin, int32_t n_elts, int32_t n_cat, int32_t su,
+                           uint32_t *__restrict__ evoff, uint32_t *__restrict__ liveoff) {
     for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e <= n_cat; e += gridDim.x * blockDim.x) {
-        uint32_t c = 0;
+        uint32_t c = 0, live = 0;
         if (e < n_cat)
-            for (int j = 0; j < n_elts; ++j) c += dat[(int64_t)j * n_cat + e] >= 0;
+            for (int j = 0; j < n_elts; ++j) {
+                const int32_t r = dat[(int64_t)j * n_cat + e];
+                if (r < 0) continue;
+                ++c;
+                live += row_cannot_pay(raw[elt_row_off[elt_begin] + r], elts[elt_begin + j], su)
+                            ? 0u : 1u;
+            }
         evoff[e] = c;
+        liveoff[e] = live;
     }
 }
 
@@ -280,7 +300,8 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
                           const int64_t *__restrict__ elt_row_off, const EltDev *__restrict__ elts,
                           LayerDev *__restrict__ layer, int32_t n_cat, int32_t su,
                           const uint32_t *__restrict__ evoff, uint32_t *__restrict__ live_out,
-                          RowQ *__restrict__ rowq,
+                          const uint32_t *__restrict__ liveoff, RowQ *__restrict__ rowq,
+                          RowF *__restrict__ rowf,
                           float *__restrict__ row_mean, float *__restrict__ row_cfrac,
                           uint32_t *__restrict__ row_meta, double *__restrict__ row_lnb,
                           float *__restrict__ otab) {
@@ -288,21 +309,18 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
     uint32_t fl_or = 0;
     for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_cat; e += gridDim.x * blockDim.x) {
         int64_t pos = L.row_base + evoff[e];
+        int64_t fpos = L.row_base + liveoff[e];       // compact record of the next paying row
         uint32_t live = 0;
         float X = 0.0f;
         // rows that can pay first, then the rows whose ELT terms give 0 for
-        // every draw (a loss never exceeds its scale: max_l, or the mean when
-        // there is no draw; scale <= retention, a zero limit or a zero share
-        // make share * min(max(loss - R, 0), L) exactly 0)
+        // every draw (row_cannot_pay)
         for (int pass = 0; pass < 2; ++pass)
             for (int j = 0; j < L.n_elts; ++j) {
                 const int32_t r = dat[(int64_t)j * n_cat + e];
                 if (r < 0) continue;
                 const RawRow rr = raw[elt_row_off[L.elt_begin] + r];
                 const EltDev ed = elts[L.elt_begin + j];
-                const bool det = !su || (double)rr.sigma_i + (double)rr.sigma_c == 0.0;
-                const float scale = det ? rr.mean : rr.max_loss;
-                const bool dead = scale <= ed.retention || ed.limit == 0.0f || ed.share == 0.0f;
+                const bool dead = row_cannot_pay(rr, ed, su);
                 if (dead != (pass == 1)) continue;
                 RowQ q;
                 uint32_t f;
@@ -315,11 +333,23 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
                 row_cfrac[pos] = cf;
                 row_meta[pos] = f | (uint32_t)j;
                 fl_or |= f & ROW_FLAGS;
+                if (!dead) {
+                    RowF F;
+                    F.scale = q.scale;
+                    F.a = q.a;
+                    F.b = q.b;
+                    F.lnb = q.lnb;
+                    F.meta = f | (uint32_t)j;
+                    F.cfrac = cf;
+                    F.row = (uint32_t)(pos - L.row_base);
+                    F.pad = 0u;
+                    rowf[fpos++] = F;
+                }
                 ++pos;
                 live += dead ? 0u : 1u;
                 X += ed.share * clampf_terms(rr.mean, ed.retention, ed.limit);
             }
-        live_out[2 * e] = evoff[e];
+        live_out[2 * e] = liveoff[e];
         live_out[2 * e + 1] = live;
         if (otab) otab[L.otab_base + e] = clampf_terms(X, L.occ_r, L.occ_l);
     }
@@ -536,6 +566,7 @@ struct SuArgs {
     const EltDev *elts;
     const uint32_t *evoff;
     const RowQ *rowq;
+    const RowF *rowf;
     const float *row_mean;
     const float *row_cfrac;
     const uint32_t *row_meta;
@@ -641,9 +672,27 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                 if (lane < cnt) {
                     const uint2 e = Q[(h + lane) & kQMask];
                     const uint32_t kl = e.x, row = e.y;
-                    // the row's flags and Beta parameters in flight together
-                    const uint32_t meta = A.row_meta[row];
-                    const RowQ q = A.rowq[row];
+                    // the row's flags and Beta parameters: one compact record in
+                    // the fast passes (row indexes the paying rows), the per-row
+                    // arrays in the diagnostic pass (row indexes all rows)
+                    uint32_t meta, orow;
+                    RowQ q;
+                    float cfrac;
+                    if (DIAG) {
+                        meta = A.row_meta[row];
+                        q = A.rowq[row];
+                        cfrac = A.row_cfrac[row];
+                        orow = row;
+                    } else {
+                        const RowF F = A.rowf[row];
+                        meta = F.meta;
+                        q.scale = F.scale;
+                        q.a = F.a;
+                        q.b = F.b;
+                        q.lnb = F.lnb;
+                        cfrac = F.cfrac;
+                        orow = (uint32_t)rb0 + F.row;
+                    }
                     const uint32_t ei = meta & 0xffffu;
                     const EltDev ed = elt_lds ? El[ei] : A.elts[L.elt_begin + ei];
                     float loss = 0.0f;
@@ -662,7 +711,7 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                                L.program_id, ev, keys, &jI, &jC);
                         float z, zc;
                         if (REDO) {
-                            hit_z<float>(meta, jI, jC, A.row_cfrac[row], &z, &zc);
+                            hit_z<float>(meta, jI, jC, cfrac, &z, &zc);
                         } else {
                             const uint32_t j = (meta & ROW_CONLY) ? jC : jI;
                             z = (float)j * 5.9604644775390625e-08f;
@@ -678,10 +727,10 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         if (need64) {
                             if (REDO) {
                                 double z64, zc64;
-                                hit_z<double>(meta, jI, jC, (double)A.row_cfrac[row], &z64, &zc64);
+                                hit_z<double>(meta, jI, jC, (double)cfrac, &z64, &zc64);
                                 bool ok;
                                 const double x = beta_quantile64((double)q.a, (double)q.b,
-                                                                 A.row_lnb[row], z64, zc64, &ok);
+                                                                 A.row_lnb[orow], z64, zc64, &ok);
                                 if (!ok) report(A.status, ARA_E_NUMERIC, ti, seg + kl, ed.elt_id);
                                 loss = (float)((double)q.scale * x);
                             } else {
@@ -832,6 +881,7 @@ __device__ __forceinline__ void batch_view(const BatchArgs &B, int p, SuArgs &A,
     A.elts = P.elts;
     A.evoff = P.evoff;
     A.rowq = P.rowq;
+    A.rowf = P.rowf;
     A.row_mean = P.row_mean;
     A.row_cfrac = P.row_cfrac;
     A.row_meta = P.row_meta;
@@ -1017,7 +1067,8 @@ hipError_t launch_check_rows(const RawRow *raw, int64_t n, int32_t n_cat, int32_
 
 hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, const EltDev *elts,
                               LayerDev *d_layer, const LayerDev &h_layer, int32_t n_cat, int32_t su,
-                              int32_t *dat, uint32_t *evoff, RowQ *rowq, float *row_mean,
+                              int32_t *dat, uint32_t *evoff, uint32_t *liveoff, RowQ *rowq,
+                              RowF *rowf, float *row_mean,
                               float *row_cfrac, uint32_t *row_meta, double *row_lnb, float *otab,
                               Status *st, hipStream_t s) {
     const int64_t nd = (int64_t)h_layer.n_elts * n_cat;
@@ -1028,11 +1079,13 @@ hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, con
                            raw, elt_row_off, h_layer.elt_begin, h_layer.n_elts, n_cat, dat, st);
     uint32_t *eo = evoff + h_layer.evoff_base;
     hipLaunchKernelGGL(k_ev_count, dim3(grid_for((int64_t)n_cat + 1, 256)), dim3(256), 0, s, dat,
-                       h_layer.n_elts, n_cat, eo);
+                       raw, elt_row_off, elts, h_layer.elt_begin, h_layer.n_elts, n_cat, su, eo,
+                       liveoff);
     hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, eo, (int64_t)n_cat + 1);
+    hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, liveoff, (int64_t)n_cat + 1);
     hipLaunchKernelGGL(k_ev_fill, dim3(grid_for(n_cat, 256)), dim3(256), 0, s, dat, raw,
-                       elt_row_off, elts, d_layer, n_cat, su, eo, evoff + h_layer.live_base, rowq,
-                       row_mean, row_cfrac, row_meta, row_lnb, otab);
+                       elt_row_off, elts, d_layer, n_cat, su, eo, evoff + h_layer.live_base,
+                       liveoff, rowq, rowf, row_mean, row_cfrac, row_meta, row_lnb, otab);
     return hipGetLastError();
 }
 
@@ -1084,7 +1137,8 @@ static hipError_t su_dispatch2(const SuLaunch &p, hipStream_t s) {
     SuArgs A;
     A.off = p.off; A.ev = p.ev; A.trial_begin = p.trial_begin; A.trial_count = p.trial_count;
     A.layers = p.layers; A.n_layers = p.n_layers; A.elts = p.elts; A.evoff = p.evoff;
-    A.rowq = p.rowq; A.row_mean = p.row_mean; A.row_cfrac = p.row_cfrac; A.row_meta = p.row_meta;
+    A.rowq = p.rowq; A.rowf = p.rowf; A.row_mean = p.row_mean; A.row_cfrac = p.row_cfrac;
+    A.row_meta = p.row_meta;
     A.row_lnb = p.row_lnb;
     A.tail_band = p.tail_band; A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf;
     A.hits = p.hits; A.hit_chk = p.hit_chk; A.status = p.status;
