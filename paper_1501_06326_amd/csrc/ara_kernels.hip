@@ -751,23 +751,35 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                 __syncthreads();
             };
 
+            // The fast pass enqueues only the rows that can pay, from the
+            // per-event (first record, count) pairs; the diagnostic pass
+            // visits every row so it counts every non-zero lookup.  The fast
+            // pass keeps its loads one chunk ahead: the next chunk's pairs
+            // and the event ids of the chunk after that are in flight while
+            // this chunk's hits are drawn.
+            const int32_t *evs = A.ev + o0 + seg;
+            const uint2 *lpairs = reinterpret_cast<const uint2 *>(A.evoff + L.live_base);
+            uint2 pr_next = make_uint2(0u, 0u);
+            int32_t e_after = -1;
+            if (!DIAG) {
+                if (lane < segn) pr_next = lpairs[evs[lane]];
+                if (kWave + lane < segn) e_after = evs[kWave + lane];
+            }
             for (int c = 0; c < segn && !abandon; c += kWave) {
                 const int kl = c + lane;
                 const bool valid = kl < segn;
                 uint32_t rb = 0, cnt = 0;
-                if (valid) {
-                    // the fast pass enqueues only the rows that can pay (they
-                    // come first); the diagnostic pass visits every row so it
-                    // counts every non-zero lookup
-                    const int32_t E = A.ev[o0 + seg + kl];
-                    if (DIAG) {
+                if (DIAG) {
+                    if (valid) {
+                        const int32_t E = evs[kl];
                         rb = eo[E];
                         cnt = eo[E + 1] - rb;
-                    } else {
-                        const uint2 pr = reinterpret_cast<const uint2 *>(A.evoff + L.live_base)[E];
-                        rb = pr.x;
-                        cnt = pr.y;
                     }
+                } else {
+                    rb = pr_next.x;
+                    cnt = pr_next.y;                  // zero past the segment's end
+                    pr_next = e_after >= 0 ? lpairs[e_after] : make_uint2(0u, 0u);
+                    e_after = (c + 2 * kWave + lane < segn) ? evs[c + 2 * kWave + lane] : -1;
                 }
                 uint32_t done = 0;
                 while (!abandon) {
