@@ -47,14 +47,18 @@ __device__ __forceinline__ double clampd_terms(double x, double r, double l) {
 
 // exclusive prefix sum of v over the 64 lanes of the wavefront (lane order)
 __device__ __forceinline__ int wave_excl_scan(int v, int *total) {
-    const int lane = threadIdx.x & 63;
+    // Inclusive prefix sum over the wavefront with DPP moves: shifts within
+    // each row of 16 lanes (lanes shifted in from outside the row read 0),
+    // then lane 15 of rows 0 and 2 added into rows 1 and 3, then lane 31
+    // added into rows 2 and 3 (the other rows keep the 0 given as old).
     int s = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int o = __shfl_up(s, d, 64);
-        if (lane >= d) s += o;
-    }
-    *total = __shfl(s, 63, 64);
+    s += __builtin_amdgcn_update_dpp(0, s, 0x111, 0xf, 0xf, true);   // row_shr:1
+    s += __builtin_amdgcn_update_dpp(0, s, 0x112, 0xf, 0xf, true);   // row_shr:2
+    s += __builtin_amdgcn_update_dpp(0, s, 0x114, 0xf, 0xf, true);   // row_shr:4
+    s += __builtin_amdgcn_update_dpp(0, s, 0x118, 0xf, 0xf, true);   // row_shr:8
+    s += __builtin_amdgcn_update_dpp(0, s, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    s += __builtin_amdgcn_update_dpp(0, s, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    *total = __builtin_amdgcn_readlane(s, 63);
     return s - v;
 }
 
@@ -786,7 +790,6 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                     const int take = (int)min(cnt - done, (uint32_t)kPerLane);
                     int tot;
                     const int excl = wave_excl_scan(take, &tot);
-                    if (tot == 0) break;
                     for (int j = 0; j < take; ++j)
                         Q[(qt + excl + j) & kQMask] =
                             make_uint2((uint32_t)kl, (uint32_t)(rb0 + rb + done + j));
@@ -796,6 +799,7 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         run_batch(qh, kWave);
                         qh += kWave;
                     }
+                    if (!__any(done < cnt)) break;
                 }
             }
             if (!abandon && qt != qh) run_batch(qh, (int)(qt - qh));
