@@ -101,16 +101,17 @@ __device__ __forceinline__ float log2_1m(float x, float w) {
 // Evaluated backward from term n (more accurate in FP32 than the forward
 // recurrence) without divisions: with d_j = p_j / q_j and K_j = N_j / D_j,
 // N_j = q_j N_{j+1} + p_j D_{j+1}, D_j = q_j N_{j+1}.  Terms go in pairs
-// (2m, 2m-1) with no branches; n (even) comes from the row (enough terms at
-// the slowest point of the branch, see cf_terms); lanes with fewer terms
-// than the batch maximum nmax (even, wave-uniform) leave their (N, D) at the
-// start value until their first term.  Rescaled every pair.  Returns N, D.
+// (2m, 2m-1); n (even) comes from the row (enough terms at the slowest
+// point of the branch, see cf_terms); lanes with fewer terms than the batch
+// maximum nmax (even, wave-uniform) leave their (N, D) at the start value
+// until their first term, a select that is skipped when every lane needs
+// nmax terms.  Rescaled every pair.  Returns N, D.
 __device__ __forceinline__ void beta_cf32(float a, float b, float x, int n, int nmax, float *Nout,
                                           float *Dout) {
     float N = 1.0f, D = 1.0f;
     const float am1 = a - 1.0f, apbm1 = (a + b) - 1.0f;
-    float fm = (float)(nmax >> 1);           // exact small integer, stepped down exactly
-    for (int m = nmax >> 1; m >= 1; --m, fm -= 1.0f) {
+    // one pair of terms (2m, 2m-1), rescaled to N = 1
+    auto pair = [&](float fm, float *Dn) {
         // even term 2m: p = m (b - m) x, q = (a + 2m - 1)(a + 2m) = te (te + 1)
         const float te = fmaf(2.0f, fm, am1);
         const float qe = fmaf(te, te, te);
@@ -118,12 +119,22 @@ __device__ __forceinline__ void beta_cf32(float a, float b, float x, int n, int 
         // odd term 2m-1: p = -(a+m-1)(a+b+m-1) x, q = (a+2m-2)(a+2m-1) = (te - 1) te
         const float qo = fmaf(te, te, -te);
         const float po = -(am1 + fm) * (apbm1 + fm) * x;
-        const bool on = 2 * m <= n;
         const float N1 = fmaf(qe, N, pe * D), D1 = qe * N;
         const float N2 = fmaf(qo, N1, po * D1), D2 = qo * N1;
-        const float s = rcp_f(N2);
-        N = on ? 1.0f : N;
-        D = on ? D2 * s : D;
+        *Dn = D2 * rcp_f(N2);
+    };
+    float fm = (float)(nmax >> 1);           // exact small integer, stepped down exactly
+    if (__all(n >= nmax)) {
+        // every lane takes every term (the usual case: one shape per batch)
+        for (int m = nmax >> 1; m >= 1; --m, fm -= 1.0f) pair(fm, &D);
+    } else {
+        for (int m = nmax >> 1; m >= 1; --m, fm -= 1.0f) {
+            float Dn;
+            pair(fm, &Dn);
+            const bool on = 2 * m <= n;
+            N = on ? 1.0f : N;
+            D = on ? Dn : D;
+        }
     }
     *Nout = N;
     *Dout = D;
