@@ -48,7 +48,7 @@ PEAK_VALU_TOPS = 157.3 / 2.0
 # lookup whose row can pay (its largest possible loss exceeds the ELT
 # retention, limit and share non-zero); the other non-zero lookups add
 # exactly 0 and are skipped.
-VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "694"))
+VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "594"))
 
 # HBM-side traffic of one launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # of this workload (profiles/ara_su_full_counters.md), each scaled by what the
@@ -56,9 +56,9 @@ VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "694"))
 # 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
 # the counters were taken with; null otherwise.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "7d94c68c25e854c9153a9538acd5e14b2c56ea076a6643c872c0c2237ab43779",
-    "su_main_bytes": 75.995e9 + 0.0917e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0866e9 + 0.0254e9,        # k_ara_pu: fetch + write, 1M trials
+    "sources_sha256": "02e8abfcb9ac0dc07a8bec7123297ba381b8aa975d86c582af6af0582dbdafbf",
+    "su_main_bytes": 27.261e9 + 0.1067e9,   # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0866e9 + 0.0256e9,        # k_ara_pu: fetch + write, 1M trials
 }
 
 
