@@ -518,8 +518,9 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
             p.occ_view = o.d_occ_view;
             p.occ_stride = o.occ_view_stride;
             p.status = ctx->d_status;
-            int64_t blocks = (o.trial_count + 3) / 4;
-            int64_t g = blocks < (int64_t)ctx->n_cu * 16 ? blocks : (int64_t)ctx->n_cu * 16;
+            // blocks of 16 wavefronts, two resident per CU (LDS table <= 60 KB)
+            int64_t blocks = (o.trial_count + 15) / 16;
+            int64_t g = blocks < (int64_t)ctx->n_cu * 2 ? blocks : (int64_t)ctx->n_cu * 2;
             p.grid = (int)(g < 1 ? 1 : g);
             ARA_HIP(ctx, launch_pu(p, o.sum_mode, f64out, s));
         }

@@ -470,11 +470,14 @@ __global__ __launch_bounds__(256) void k_pu_occ_view(PuArgs P) {
     }
 }
 
-// One wavefront per trial (persistent grid-stride over trials).  Event ids
-// are streamed with 16-byte loads (after a scalar head that reaches 16-byte
+// One wavefront per trial (persistent grid-stride over trials).  With the
+// table in LDS a block is 16 wavefronts sharing one copy, two blocks per CU
+// (32 wavefronts: the LDS copy per wavefront is what limited occupancy);
+// with the table in global memory blocks are 4 wavefronts.  Event ids are
+// streamed with 16-byte loads (after a scalar head that reaches 16-byte
 // alignment), four loads in flight per lane.
 template <int MODE, bool F64OUT, int TAB>
-__global__ __launch_bounds__(256) void k_ara_pu(PuArgs P) {
+__device__ __forceinline__ void pu_trials(const PuArgs &P) {
     extern __shared__ uint32_t sm[];
     const int32_t nw = (P.n_cat + 31) >> 5;
     float *tab = (float *)sm;
@@ -543,6 +546,18 @@ __global__ __launch_bounds__(256) void k_ara_pu(PuArgs P) {
             }
         }
     }
+}
+
+// Table in LDS: 16 wavefronts per block, 8 per SIMD (two blocks per CU).
+template <int MODE, bool F64OUT, int TAB>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_ara_pu(PuArgs P) {
+    pu_trials<MODE, F64OUT, TAB>(P);
+}
+
+// Table in global memory (catalogues too large for LDS): 4 wavefronts per block.
+template <int MODE, bool F64OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_ara_pu_global(PuArgs P) {
+    pu_trials<MODE, F64OUT, TAB_GLOBAL>(P);
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,17 +1140,21 @@ static hipError_t pu_dispatch(const PuLaunch &p, hipStream_t s) {
     A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf; A.accumulate_pf = p.accumulate_pf;
     A.occ_view = p.occ_view; A.occ_stride = p.occ_stride; A.status = p.status;
     if (p.occ_view)
-        hipLaunchKernelGGL((k_pu_occ_view<F64OUT>), dim3(p.grid), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_pu_occ_view<F64OUT>), dim3(p.grid * 4), dim3(256), 0, s, A);
     const size_t nw = ((size_t)p.n_cat + 31) / 32;
     const size_t dense = (size_t)p.n_cat * sizeof(float);
     const size_t sparse = (2 * nw + 1 + (size_t)p.nnz) * sizeof(uint32_t);
-    const dim3 g(p.grid), b(256);
-    if (dense <= 32 * 1024)
+    // p.grid counts blocks of 16 wavefronts (two per CU at most)
+    const dim3 g(p.grid), b(1024);
+    if (dense <= 32 * 1024) {
         hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, TAB_LDS_DENSE>), g, b, dense, s, A);
-    else if (sparse <= 60 * 1024)
+    } else if (sparse <= 60 * 1024) {
         hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, TAB_LDS_SPARSE>), g, b, sparse, s, A);
-    else
-        hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, TAB_GLOBAL>), g, b, 0, s, A);
+    } else {
+        const int64_t g4 = (p.trial_count + 3) / 4 < (int64_t)p.grid * 8 ? (p.trial_count + 3) / 4
+                                                                         : (int64_t)p.grid * 8;
+        hipLaunchKernelGGL((k_ara_pu_global<MODE, F64OUT>), dim3((unsigned)g4), dim3(256), 0, s, A);
+    }
     return hipGetLastError();
 }
 
