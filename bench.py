@@ -56,9 +56,9 @@ VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "594"))
 # 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
 # the counters were taken with; null otherwise.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "02e8abfcb9ac0dc07a8bec7123297ba381b8aa975d86c582af6af0582dbdafbf",
-    "su_main_bytes": 27.261e9 + 0.1067e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0866e9 + 0.0256e9,        # k_ara_pu: fetch + write, 1M trials
+    "sources_sha256": "80180e9e35fefa549678146664d6098d005f12f810a6d706278e5081c5d2cccc",
+    "su_main_bytes": 27.260e9 + 0.1065e9,   # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0882e9 + 0.0305e9,        # k_ara_pu: fetch + write, 1M trials
 }
 
 
