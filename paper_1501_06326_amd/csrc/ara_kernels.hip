@@ -13,11 +13,16 @@
 //        gather-sum over its event ids followed by the aggregate terms.
 //      - k_ara_su: secondary uncertainty.  One wavefront per trial; lanes
 //        read consecutive occurrences, look each up in the layer's event-major
-//        rows, and append the non-zero hits to an LDS queue; the queue is
-//        drained 64 hits at a time so every lane of a batch draws, inverts
-//        the Beta CDF and applies the ELT terms on real work (the paper's
-//        "convergence switching" idea applied to SIMD lanes).  Hits in the
-//        FP64 tail band go to a second queue drained by the FP64 path.
+//        rows, and append the hits to an LDS queue (the fast pass only the
+//        rows that can pay: the others add exactly 0); the queue is drained
+//        64 hits at a time so every lane of a batch draws, inverts the Beta
+//        CDF and applies the ELT terms on real work (the paper's
+//        "convergence switching" idea applied to SIMD lanes).  A trial with
+//        a hit that needs the FP64 quantile (tail band, shapes outside the
+//        FP32 domain, the two-normal mix, FP32 non-convergence) is handed to
+//        k_ara_su_redo, which runs it again with the FP64 path in place.
+//      - k_ara_batch / k_ara_batch_items: the same trial code over
+//        (portfolio, trial tile) work items of many portfolios at once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
