@@ -168,6 +168,23 @@ def test_determinism_and_slicing(ara):
     assert np.array_equal(np.concatenate([c1, c2], axis=1), a)
 
 
+@pytest.mark.parametrize("su", [False, True])
+def test_small_trial_ranges(ara, su):
+    """Ranges far below one block of wavefronts (1, 7, 17 trials, odd starts)
+    give the same YLT entries as the whole run: a trial's result does not
+    depend on the grid that computed it."""
+    w = config_small(su=su, n_trials=3000)
+    say("small trial ranges", su)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    full = ara.run(y, p)["ylt"].cpu().numpy()
+    for tb, tc in [(0, 1), (5, 7), (100, 17), (2983, 17), (1, 2999)]:
+        part = ara.run(y, p, trial_begin=tb, trial_count=tc)["ylt"].cpu().numpy()
+        assert np.array_equal(part, full[:, tb:tb + tc]), (tb, tc)
+    ara.free_portfolio(p)
+    ara.free_yet(y)
+
+
 @pytest.mark.parametrize("mode", ["naive32", "kahan32", "f64"])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_sum_modes(ara, mode, dtype):
