@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--oracle-trials", type=int, default=3000, help="precision mode")
     ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
     ap.add_argument("--graph", action="store_true", help="batched mode: also time a graph replay")
-    ap.add_argument("--requests", type=int, default=1000, help="served mode: requests per load")
+    ap.add_argument("--requests", type=int, default=2000, help="served mode: requests per load")
     ap.add_argument("--loads", default="0.5,0.8,0.95,1.5",
                     help="served mode: offered loads as fractions of one-at-a-time capacity")
     ap.add_argument("--max-inflight", type=int, default=2, help="served mode: streams")
