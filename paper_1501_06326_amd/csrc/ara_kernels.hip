@@ -137,6 +137,7 @@ __global__ __launch_bounds__(256) void k_validate_yet(const int64_t *__restrict_
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
     if (wid == 0 && lane == 0 && off[0] != 0) report(st, ARA_E_OFFSETS_NOT_MONOTONE, 0, off[0], 0);
     const int64_t n_occ = off[n_trials];
+    unsigned long long longest = 0;   // this wavefront's longest trial (one atomic per wavefront)
     for (int64_t t = wid; t < n_trials; t += nw) {
         const int64_t a = off[t], b = off[t + 1];
         // a trial is read only when it lies inside [0, offsets[n_trials])
@@ -144,14 +145,34 @@ __global__ __launch_bounds__(256) void k_validate_yet(const int64_t *__restrict_
             if (lane == 0) report(st, ARA_E_OFFSETS_NOT_MONOTONE, t, a, b);
             continue;
         }
-        if (lane == 0) atomicMax(max_len, (unsigned long long)(b - a));
-        for (int64_t j = a + lane; j < b; j += 64) {
-            const int32_t e = ev[j];
-            if (e < 0 || e >= n_cat) report(st, ARA_E_EVENT_ID_RANGE, t, j - a, e);
-            if (times && j + 1 < b && !(times[j] <= times[j + 1]))
-                report(st, ARA_E_TIMES_UNSORTED, t, j - a, 0);
+        if ((unsigned long long)(b - a) > longest) longest = (unsigned long long)(b - a);
+        // four ids (and time pairs) in flight per lane: every load takes an
+        // index inside the trial (a lane past its end reads its first
+        // element) so they issue together; the checks use the real index
+        for (int64_t j0 = a + lane; j0 < b; j0 += 4 * 64) {
+            int32_t e[4];
+            float t0[4], t1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t j = j0 + 64 * u;
+                const int64_t jj = j < b ? j : a;
+                e[u] = ev[jj];
+                if (times) {
+                    t0[u] = times[jj];
+                    t1[u] = times[jj + 1 < b ? jj + 1 : jj];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t j = j0 + 64 * u;
+                if (j < b && (e[u] < 0 || e[u] >= n_cat))
+                    report(st, ARA_E_EVENT_ID_RANGE, t, j - a, e[u]);
+                if (times && j + 1 < b && !(t0[u] <= t1[u]))
+                    report(st, ARA_E_TIMES_UNSORTED, t, j - a, 0);
+            }
         }
     }
+    if (lane == 0 && longest > 0) atomicMax(max_len, longest);
 }
 
 // ---------------------------------------------------------------------------
@@ -1083,7 +1104,10 @@ static inline int grid_for(int64_t n, int block, int cap = 65536) {
 hipError_t launch_validate_yet(const int64_t *off, const int32_t *ev, const float *times,
                                int64_t n_trials, int32_t n_cat, Status *st,
                                unsigned long long *max_len, hipStream_t s) {
-    const int g = grid_for(n_trials, 4, 262144);
+    // a resident grid (8 blocks of 4 wavefronts per CU of the largest part)
+    // that strides over the trials: one atomic per wavefront for the longest
+    // trial, not one per trial on a single address
+    const int g = grid_for(n_trials, 4, 2048);
     hipLaunchKernelGGL(k_validate_yet, dim3(g), dim3(256), 0, s, off, ev, times, n_trials, n_cat,
                        st, max_len);
     return hipGetLastError();
