@@ -69,7 +69,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t layers, elts, evoff, liveoff, rowq, rowf, row_mean, row_cfrac, row_meta, row_lnb, otab,
         sp_bits, sp_rank,
-        sp_vals, raw, eltoff, dat, total;
+        sp_vals, raw, rawfit, eltoff, dat, total;
     int64_t n_rows = 0;
     int32_t n_elts = 0, max_layer_elts = 0;
 };
@@ -130,6 +130,7 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
     L->sp_rank = o; o += pu ? align256(sizeof(uint32_t) * (size_t)nl * (nw + 1)) : 0;
     L->sp_vals = o; o += pu ? align256(sizeof(float) * (size_t)nl * n_cat) : 0;
     L->raw = o; o += align256(sizeof(RawRow) * (size_t)(rows ? rows : 1));
+    L->rawfit = o; o += align256(sizeof(RowFit) * (size_t)(rows ? rows : 1));
     L->eltoff = o; o += align256(sizeof(int64_t) * (size_t)(ne + 1));
     L->dat = o; o += align256(sizeof(int32_t) * (size_t)(mx ? mx : 1) * n_cat);
     L->total = o;
@@ -414,9 +415,12 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
         ara_status cs = check_status(ctx, s, "ara_load_portfolio");
         if (cs != ARA_OK) return cleanup(cs);
     }
+    RowFit *d_fit = (RowFit *)(w + L.rawfit);
+    ARA_HIP_P(launch_fit_rows(d_raw, L.n_rows, p->su_enabled, d_fit, s));
     const size_t nwc = ((size_t)n_catalogue + 31) / 32;
     for (int l = 0; l < nl; ++l) {
-        ARA_HIP_P(launch_build_layer(d_raw, d_eltoff, p->d_elts, p->d_layers + l, hl[l], n_catalogue,
+        ARA_HIP_P(launch_build_layer(d_raw, d_fit, d_eltoff, p->d_elts, p->d_layers + l, hl[l],
+                                     n_catalogue,
                                      p->su_enabled, d_dat, p->d_evoff,
                                      (uint32_t *)(w + L.liveoff) + (size_t)l * ((size_t)n_catalogue + 1),
                                      p->d_rowq, p->d_rowf, p->d_row_mean,

@@ -70,6 +70,14 @@ struct RawRow {
     float mean, sigma_i, sigma_c, max_loss;
 };
 
+// The Beta fit of one raw row (build staging, indexed like the raw rows).
+struct RowFit {
+    RowQ q;
+    uint32_t flags;
+    float cfrac;
+    double lnb;
+};
+
 // Context-owned device status words.
 struct Status {
     int32_t code;          // 0 or an ara_status of the first failure

@@ -99,7 +99,9 @@ hipError_t launch_validate_yet(const int64_t *off, const int32_t *ev, const floa
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_check_rows(const RawRow *raw, int64_t n, int32_t n_cat, int32_t su, Status *st,
                              hipStream_t s);
-hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, const EltDev *elts,
+hipError_t launch_fit_rows(const RawRow *raw, int64_t n, int32_t su, RowFit *fit, hipStream_t s);
+hipError_t launch_build_layer(const RawRow *raw, const RowFit *fit, const int64_t *elt_row_off,
+                              const EltDev *elts,
                               LayerDev *d_layer, const LayerDev &h_layer, int32_t n_cat, int32_t su,
                               int32_t *dat, uint32_t *evoff, uint32_t *liveoff, RowQ *rowq,
                               RowF *rowf, float *row_mean,

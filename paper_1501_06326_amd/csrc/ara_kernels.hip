@@ -323,10 +323,24 @@ __device__ void fit_row(const RawRow &r, int32_t su, RowQ *q, uint32_t *flags, f
     *flags = f;
 }
 
+// The Beta fit of every raw row of the portfolio, one thread per row: the
+// fit (FP64 moment fit, ln B and the continued-fraction term counts) is the
+// costly part of the build and does not depend on where the row lands.
+__global__ void k_fit_rows(const RawRow *__restrict__ raw, int64_t n, int32_t su,
+                           RowFit *__restrict__ fit) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        RowFit f;
+        fit_row(raw[i], su, &f.q, &f.flags, &f.cfrac, &f.lnb);
+        fit[i] = f;
+    }
+}
+
 // Event-major rows of one layer: for every catalogue event, its rows in the
 // layer's ELT order, with the fitted Beta constants; also the per-event
 // occurrence loss table when secondary uncertainty is off.
 __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restrict__ raw,
+                          const RowFit *__restrict__ fit,
                           const int64_t *__restrict__ elt_row_off, const EltDev *__restrict__ elts,
                           LayerDev *__restrict__ layer, int32_t n_cat, int32_t su,
                           const uint32_t *__restrict__ evoff, uint32_t *__restrict__ live_out,
@@ -348,15 +362,16 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
             for (int j = 0; j < L.n_elts; ++j) {
                 const int32_t r = dat[(int64_t)j * n_cat + e];
                 if (r < 0) continue;
-                const RawRow rr = raw[elt_row_off[L.elt_begin] + r];
+                const int64_t ri = elt_row_off[L.elt_begin] + r;
+                const RawRow rr = raw[ri];
                 const EltDev ed = elts[L.elt_begin + j];
                 const bool dead = row_cannot_pay(rr, ed, su);
                 if (dead != (pass == 1)) continue;
-                RowQ q;
-                uint32_t f;
-                float cf;
-                double lb;
-                fit_row(rr, su, &q, &f, &cf, &lb);
+                const RowFit rf = fit[ri];
+                const RowQ q = rf.q;
+                const uint32_t f = rf.flags;
+                const float cf = rf.cfrac;
+                const double lb = rf.lnb;
                 row_lnb[pos] = lb;
                 rowq[pos] = q;
                 row_mean[pos] = rr.mean;
@@ -1125,7 +1140,14 @@ hipError_t launch_check_rows(const RawRow *raw, int64_t n, int32_t n_cat, int32_
     return hipGetLastError();
 }
 
-hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, const EltDev *elts,
+hipError_t launch_fit_rows(const RawRow *raw, int64_t n, int32_t su, RowFit *fit, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_fit_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, raw, n, su, fit);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_layer(const RawRow *raw, const RowFit *fit, const int64_t *elt_row_off,
+                              const EltDev *elts,
                               LayerDev *d_layer, const LayerDev &h_layer, int32_t n_cat, int32_t su,
                               int32_t *dat, uint32_t *evoff, uint32_t *liveoff, RowQ *rowq,
                               RowF *rowf, float *row_mean,
@@ -1143,7 +1165,7 @@ hipError_t launch_build_layer(const RawRow *raw, const int64_t *elt_row_off, con
                        liveoff);
     hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, eo, (int64_t)n_cat + 1);
     hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, liveoff, (int64_t)n_cat + 1);
-    hipLaunchKernelGGL(k_ev_fill, dim3(grid_for(n_cat, 256)), dim3(256), 0, s, dat, raw,
+    hipLaunchKernelGGL(k_ev_fill, dim3(grid_for(n_cat, 256)), dim3(256), 0, s, dat, raw, fit,
                        elt_row_off, elts, d_layer, n_cat, su, eo, evoff + h_layer.live_base,
                        liveoff, rowq, rowf, row_mean, row_cfrac, row_meta, row_lnb, otab);
     return hipGetLastError();
