@@ -251,27 +251,39 @@ __global__ void k_ev_count(const int32_t *__restrict__ dat, const RawRow *__rest
     }
 }
 
-// In-place exclusive scan of n values with one 1024-thread block.
+// In-place exclusive scan of n values with one 1024-thread block: rounds of
+// 8 tiles of 1024 values, loaded together (coalesced) and scanned tile by
+// tile in order with a wavefront scan and the 16 wavefront totals in LDS.
 __global__ __launch_bounds__(1024) void k_scan_excl_u32(uint32_t *p, int64_t n) {
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t a = tid * per, b = a + per < n ? a + per : n;
-    uint32_t s = 0;
-    for (int64_t i = a; i < b; ++i) s += p[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        uint32_t v = tid >= d ? part[tid - d] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - s;
-    for (int64_t i = a; i < b; ++i) {
-        const uint32_t v = p[i];
-        p[i] = run;
-        run += v;
+    constexpr int kTiles = 8;
+    __shared__ uint32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t carry = 0;                          // sum of everything before the round
+    for (int64_t base = 0; base < n; base += (int64_t)kTiles * 1024) {
+        uint32_t v[kTiles];
+#pragma unroll
+        for (int k = 0; k < kTiles; ++k) {
+            const int64_t i = base + (int64_t)k * 1024 + tid;
+            v[k] = i < n ? p[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kTiles; ++k) {
+            int wt;
+            // the bits of a uint32 sum are those of the int32 sum
+            const uint32_t ex = (uint32_t)wave_excl_scan((int)v[k], &wt);
+            if (lane == 0) wsum[w] = (uint32_t)wt;
+            __syncthreads();
+            uint32_t before = 0, tile = 0;
+            for (int q = 0; q < 16; ++q) {
+                const uint32_t t = wsum[q];
+                before += q < w ? t : 0u;
+                tile += t;
+            }
+            const int64_t i = base + (int64_t)k * 1024 + tid;
+            if (i < n) p[i] = carry + before + ex;
+            carry += tile;
+            __syncthreads();
+        }
     }
 }
 
