@@ -56,9 +56,9 @@ VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "594"))
 # 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
 # the counters were taken with; null otherwise.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "7651faecc64810b4e7f60b4ff032b8153c783abc8b591ecaa2be1c63288c97ad",
-    "su_main_bytes": 27.260e9 + 0.1065e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0882e9 + 0.0305e9,        # k_ara_pu: fetch + write, 1M trials
+    "sources_sha256": "80c5e1ed16be783bd6d641fa5b299697d8dcad7f6aa32b0506a9f868405a0653",
+    "su_main_bytes": 27.261e9 + 0.1066e9,   # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0884e9 + 0.0304e9,        # k_ara_pu: fetch + write, 1M trials
 }
 
 
