@@ -766,7 +766,21 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         orow = (uint32_t)rb0 + F.row;
                     }
                     const uint32_t ei = meta & 0xffffu;
-                    const EltDev ed = elt_lds ? El[ei] : A.elts[L.elt_begin + ei];
+                    // the layer's ELT record: an LDS read when the layer's records
+                    // are staged (the global read is a different instruction, so the
+                    // two are not merged into one flat load)
+                    EltDev ed;
+                    if (elt_lds) {
+                        ed = El[ei];
+                    } else {
+                        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                        const u32x4 g = __builtin_nontemporal_load(
+                            reinterpret_cast<const u32x4 *>(A.elts + L.elt_begin + ei));
+                        ed.elt_id = g.x;
+                        ed.retention = __uint_as_float(g.y);
+                        ed.limit = __uint_as_float(g.z);
+                        ed.share = __uint_as_float(g.w);
+                    }
                     float loss = 0.0f;
                     if (meta & ROW_DET) {
                         loss = q.scale;
