@@ -213,7 +213,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (FP64 in the quantile tail band and the TVaR sum)",
+        "dtype": "f32 (FP64 for the TVaR sum and the quantile of shapes outside the FP32 domain)",
         "data": "synthetic (seeded numpy generator; lognormal ELT means)",
         "config": {"workload": w.name, "trials": n, "occurrences": yet.n_occ,
                    "catalogue": yet.n_catalogue, "layers": 1, "elts": 16,

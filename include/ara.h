@@ -129,7 +129,7 @@ typedef struct {
     int64_t trial_count;        /* number of trials; -1 = to the end of the YET */
     int32_t sum_mode;           /* ARA_SUM_*: how a trial's occurrence losses are summed */
     int32_t ylt_dtype;          /* ARA_F32 or ARA_F64 for both YLT outputs */
-    float tail_band;            /* z or 1-z below this use the FP64 quantile; <= 0: 2^-20 */
+    float tail_band;            /* z or 1-z below this use the FP64 quantile; <= 0: 2^-24 */
     int32_t reserved;
     int64_t *d_hits;            /* optional [n_layers][trial_count]: non-zero lookups */
     uint64_t *d_hit_chk;        /* optional [n_layers][trial_count]: sum over hits of
@@ -361,8 +361,8 @@ ara_status ara_ep_curve(ara_context *ctx, const void *d_ylt, int32_t ylt_dtype, 
 /* ---- diagnostics (used by the tests) -------------------------------------
  * ara_debug_philox: d_out[4j..4j+3] = Philox4x32-10(d_ctr[4j..4j+3], key).
  * ara_debug_beta_quantile: d_x[j] = I^-1(z_j; a_j, b_j) by the same device
- * code the analysis uses (FP32 bulk, FP64 in the tail band and for shapes the
- * FP32 path does not cover), given z and its complement zc = 1 - z (FP64
+ * code the analysis uses (FP32, FP64 below tail_band (<= 0: 2^-24) and for
+ * shapes the FP32 path does not cover), given z and its complement zc = 1 - z (FP64
  * inputs, exact grid values) and a per-entry FP32 shape; d_path[j] (may be
  * NULL) receives 0 for the FP32 path, 1 for the FP64 path. */
 ara_status ara_debug_philox(ara_context *ctx, int64_t n, const uint32_t *d_ctr, uint64_t key,

@@ -38,7 +38,11 @@ struct ara_graph {
 namespace {
 
 constexpr int kMaxRp = 256;
-constexpr float kDefaultTailBand = 9.5367431640625e-07f;   // 2^-20
+// 2^-24, the smallest draw on the grid: every draw takes the FP32 quantile
+// (its residual is taken on the smaller side, accurate to ~1e-7 down to
+// 2^-24); the FP64 path serves shapes outside the FP32 domain, sigma-capped
+// rows and FP32 non-convergence.
+constexpr float kDefaultTailBand = 5.9604644775390625e-08f;
 
 size_t run_scratch_need(int64_t trial_count) {
     return 256 + ((size_t)(trial_count > 0 ? trial_count : 1) * sizeof(int32_t) + 255) / 256 * 256;

@@ -216,8 +216,9 @@ __device__ __forceinline__ void beta_inc32(float a, float b, float lnb2, int na,
 // residual, u = r / f = r x (1-x) / front and u (log f)' = r ((a-1)(1-x) -
 // (b-1) x) / front share one reciprocal.  Stops when every lane's last
 // full-accuracy step was below 2^-10 of the root (Halley: the next error ~
-// step^3).  Returns false in *ok if it did not converge (the caller then
-// uses the FP64 path).
+// step^3); a lane keeps the iterate of its own first such step, so its
+// result does not depend on how many iterations the wavefront runs.  Returns
+// false in *ok if it did not converge (the caller then uses the FP64 path).
 __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, int na, int nb,
                                                  float z, float zc, bool *ok) {
     float x0 = beta_guess32(a, b, z, zc);
@@ -237,14 +238,19 @@ __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, i
     for (int bit = 32; bit >= 1; bit >>= 1)
         if (__any(nl >= (nmax | bit))) nmax |= bit;
     const int nhalf = max(2, ((nmax >> 1) + 1) & ~1);
+    // this lane's own half count (the wave's bounds only size the loops, so a
+    // lane's result does not depend on the lanes beside it)
+    const int nh = max(2, ((nl >> 1) + 1) & ~1);
     float x = fminf(fmaxf(x0, 1e-30f), 0.75f);
     const bool lower = Z <= 0.5f;
     const float am1 = A - 1.0f, bm1 = B - 1.0f;
     bool conv = false;
+    float xf = x;          // the lane's answer: its iterate at its own first convergence
     for (int it = 0; it < 6; ++it) {
         const int nt = it == 0 ? nhalf : nmax;
+        const int nown = it == 0 ? nh : nmax;
         float I, Ic, front;
-        beta_inc32(A, B, lnb2, min(NA, nt), min(NB, nt), nt, x, &I, &Ic, &front);
+        beta_inc32(A, B, lnb2, min(NA, nown), min(NB, nown), nt, x, &I, &Ic, &front);
         const float r = lower ? (I - Z) : (ZC - Ic);
         const float w = 1.0f - x;
         const float rf = r * rcp_f(front);
@@ -254,12 +260,15 @@ __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, i
         float xn = x - t;
         if (!(xn > 0.0f)) xn = 0.5f * x;
         if (!(xn < 1.0f)) xn = 0.5f * (x + 1.0f);
-        conv = it > 0 && fabsf(xn - x) <= 9.765625e-4f * xn;
+        if (!conv) {
+            xf = xn;
+            conv = it > 0 && fabsf(xn - x) <= 9.765625e-4f * xn;
+        }
         x = xn;
         if (__all(conv)) break;
     }
-    *ok = conv && isfinite(x);
-    return mirror ? 1.0f - x : x;
+    *ok = conv && isfinite(xf);
+    return mirror ? 1.0f - xf : xf;
 }
 
 // ---------------------------------------------------------------------------
