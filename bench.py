@@ -48,7 +48,7 @@ PEAK_VALU_TOPS = 157.3 / 2.0
 # lookup whose row can pay (its largest possible loss exceeds the ELT
 # retention, limit and share non-zero); the other non-zero lookups add
 # exactly 0 and are skipped.
-VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "594"))
+VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "588"))
 
 # HBM-side traffic of one launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # of this workload (profiles/ara_su_full_counters.md), each scaled by what the
@@ -56,9 +56,9 @@ VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "594"))
 # 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
 # the counters were taken with; null otherwise.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "80c5e1ed16be783bd6d641fa5b299697d8dcad7f6aa32b0506a9f868405a0653",
-    "su_main_bytes": 27.261e9 + 0.1066e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0884e9 + 0.0304e9,        # k_ara_pu: fetch + write, 1M trials
+    "sources_sha256": "795212e0e98730d0a6986293d8bdd2439c105f6fea148ad1cb00f71d4fd911cc",
+    "su_main_bytes": 27.248e9 + 0.1070e9,   # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0881e9 + 0.0304e9,        # k_ara_pu: fetch + write, 1M trials
 }
 
 
