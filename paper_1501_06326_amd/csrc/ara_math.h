@@ -333,6 +333,9 @@ __device__ inline double beta_solve64(double a, double b, double lnb, double z, 
         const double r = lower ? (I - z) : (zc - Ic);
         if (r == 0.0) { *ok = true; return x; }
         if (r < 0.0) lo = x; else hi = x;
+        // the root lies below 1e-300 (near-Bernoulli shapes): 0 to double
+        // precision, and the loss it scales underflows in FP32 anyway
+        if (hi <= 1e-300) { *ok = true; return 0.0; }
         const double dens = exp(ld);
         const double u = r / dens;
         const double hh = (a - 1.0) / x - (b - 1.0) / (1.0 - x);

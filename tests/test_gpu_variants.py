@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import config_full, config_small, sigma_capped
+from workloads import config_full, config_small, sigma_capped, varied_shapes
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -95,6 +95,27 @@ def test_sigma_capped_rows(ara, corr):
     w = config_small(corr=corr, n_trials=2000)
     say("sigma capped rows", corr)
     parity(ara, w.yet, sigma_capped(w.portfolio))
+
+
+@pytest.mark.parametrize("corr", [False, True])
+def test_varied_shapes(ara, corr):
+    """Every row its own shape: parity with the oracle, and the diagnostic
+    pass (which also draws the rows that cannot pay, so its batches mix other
+    draws) gives the fast pass's YLT bit for bit, as does a batch."""
+    w = config_small(corr=corr, n_trials=3000)
+    pf = varied_shapes(w.portfolio)
+    say("varied shapes", corr)
+    r, ref = parity(ara, w.yet, pf)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(pf, w.yet.n_catalogue)
+    fast = ara.run(y, p)
+    assert torch.equal(fast["ylt"], r["ylt"])
+    p0 = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    outs = ara.run_batch(y, [p0, p])
+    assert torch.equal(outs[1]["ylt"], fast["ylt"])
+    for d in (p, p0):
+        ara.free_portfolio(d)
+    ara.free_yet(y)
 
 
 @pytest.mark.parametrize("su", [True, False])

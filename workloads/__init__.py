@@ -284,6 +284,21 @@ def sigma_capped(pf: Portfolio, fraction: float = 0.3, seed: int = 8) -> Portfol
     return out
 
 
+def varied_shapes(pf: Portfolio, seed: int = 9) -> Portfolio:
+    """A copy of pf whose rows each get their own Beta shape: sigma_I = mean x
+    U(0.15, 0.9) and max = mean x U(1.5, 10), so one batch of draws mixes
+    shapes (and continued-fraction term counts) across its lanes."""
+    import copy
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed])))
+    out = copy.deepcopy(pf)
+    for layer in out.layers:
+        for e in layer.elts:
+            m = np.asarray(e.mean, np.float32)
+            e.sigma_i = (m * rng.uniform(0.15, 0.9, m.size)).astype(np.float32)
+            e.max_loss = (m * rng.uniform(1.5, 10.0, m.size)).astype(np.float32)
+    return out
+
+
 def random_layer_terms(rng: np.random.Generator, lo: float = 1e5, hi: float = 1e9):
     """Per-layer OccR, OccL, AggR, AggL, each log-uniform on [lo, hi]."""
     v = _log_uniform(rng, lo, hi, size=4)
