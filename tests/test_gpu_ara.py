@@ -8,13 +8,14 @@ Tolerances (written here, derived in the design notes):
   * PML / TVaR end to end: 1e-6 relative;
   * PML on the same YLT: bit-identical to numpy's k-th largest; TVaR 1e-12.
 """
+import json
 import math
 
 import numpy as np
 import pytest
 
 import oracle
-from tests.tiny import A, B, random_tiny_case, worked_example
+from tests.tiny import GOLDEN, A, B, golden_worked_cases, random_tiny_case, worked_example
 from workloads import config_small, make_yet
 
 torch = pytest.importorskip("torch")
@@ -103,6 +104,44 @@ def test_worked_example_exact(ara):
     r2 = ara.run(y, p2, diagnostics=True)
     assert r2["ylt"].cpu().numpy()[0].tolist() == [6.0e5, 0.0, 0.0, 3.4e6]
     assert r2["hits"].cpu().numpy()[0].tolist() == [5, 1, 0, 6]
+
+
+@pytest.mark.parametrize("corr", [False, True])
+def test_small_config_vs_stored_oracle(ara, corr):
+    """Against the oracle's stored results (tests/golden/oracle_small.json),
+    without running the oracle: hit count exact, PML / TVaR 1e-6 relative."""
+    with open(GOLDEN / "oracle_small.json") as f:
+        case = json.load(f)["cases"][int(corr)]
+    w = config_small(corr=corr)
+    assert w.name == case["workload"]
+    say("stored oracle results:", w.name)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    r = ara.run(y, p, diagnostics=True)
+    assert int(r["hits"].sum().item()) == case["hits"]
+    pml, tvar = ara.pml_tvar(r["ylt_pf"], case["return_periods"])
+    np.testing.assert_allclose(pml, case["pml"], rtol=1e-6)
+    np.testing.assert_allclose(tvar, case["tvar"], rtol=1e-6)
+    ara.free_portfolio(p)
+    ara.free_yet(y)
+
+
+def test_worked_example_golden_fixture(ara):
+    """The hand-worked fixture through both kernels: exact values."""
+    for name, yet, pf, ex in golden_worked_cases():
+        say("golden worked example:", name)
+        y = ara.load_yet(yet)
+        for su in (False, True):
+            pf.su_enabled = su
+            p = ara.load_portfolio(pf, yet.n_catalogue)
+            r = ara.run(y, p, diagnostics=su, occ_view=True)
+            assert r["ylt"].cpu().numpy()[0].tolist() == ex["ylt"], (name, su)
+            if ex["occ_view"]:
+                assert r["occ_view"].cpu().numpy()[0].tolist() == ex["occ_view"], (name, su)
+            if su:
+                assert r["hits"].cpu().numpy()[0].tolist() == ex["hits"], (name, su)
+            ara.free_portfolio(p)
+        ara.free_yet(y)
 
 
 @pytest.mark.parametrize("su", [False, True])

@@ -5,6 +5,7 @@ hand (section 2.2 terms), closed forms, exact rational brute force, library
 special functions (scipy, mpmath, statistics), rocRAND's Philox engine, and
 invariants of the method.  No expected value comes from the GPU library.
 """
+import json
 import math
 import statistics
 from fractions import Fraction
@@ -16,7 +17,8 @@ import scipy.special as sp
 import scipy.stats as st
 
 import oracle as O
-from tests.tiny import A, B, elt_from_dict, random_tiny_case, worked_example, yet_from_lists
+from tests.tiny import (GOLDEN, A, B, elt_from_dict, golden_worked_cases, random_tiny_case, worked_example,
+                        yet_from_lists)
 from workloads import INF, Layer, Portfolio, config_small, make_yet
 
 # --------------------------------------------------------------------------
@@ -107,6 +109,24 @@ def test_worked_example_variants():
     r = O.run_ara(yet, pf)
     # [B]: X = 4e5 < OccR -> 0; []: 0; [A,A,A]: S = 8.4e6 -> 3.4e6
     assert list(r["ylt"][0]) == [0.0, 0.0, 3.4e6, 6.0e5]
+
+
+def test_worked_example_golden_fixture():
+    """Every case of the hand-worked fixture, exactly (all values are dyadic
+    multiples of 1e5, so FP64 reaches them without rounding), and the exact
+    rational brute force agrees."""
+    n = 0
+    for name, yet, pf, ex in golden_worked_cases():
+        r = O.run_ara(yet, pf, occ_view=True)
+        assert r["ylt"][0].tolist() == ex["ylt"], name
+        assert r["gross"][0].tolist() == ex["gross"], name
+        assert r["hits"][0].tolist() == ex["hits"], name
+        assert r["occ_view"][0].tolist() == ex["occ_view"], name
+        ys, gs, vs = frac_ara(yet, pf)
+        assert [float(v) for v in ys[0]] == ex["ylt"], name
+        assert [float(v) for v in vs[0]] == ex["occ_view"], name
+        n += 1
+    assert n == 4
 
 
 # --------------------------------------------------------------------------
@@ -645,3 +665,25 @@ def test_generator_properties():
     assert np.all(e.sigma_i == e.mean * np.float32(0.5))
     assert np.all(e.max_loss == e.mean * np.float32(4.0))
     assert abs(np.log(e.mean).mean() - 12) < 0.1 and abs(np.log(e.mean).std() - 1.5) < 0.1
+
+
+# --------------------------------------------------------------------------
+# regression guard (not a pin): the oracle's stored results on the small
+# workload, written by tests/golden/make_oracle_small.py.  A change to the
+# oracle's arithmetic shows here and must be justified before the file is
+# rewritten.
+# --------------------------------------------------------------------------
+def test_oracle_matches_its_stored_small_results():
+    with open(GOLDEN / "oracle_small.json") as f:
+        doc = json.load(f)
+    for case in doc["cases"]:
+        w = config_small(corr=case["workload"].endswith("_corr"))
+        assert w.name == case["workload"]
+        r = O.run_ara(w.yet, w.portfolio)
+        pml, tvar = O.pml_tvar(r["ylt_pf"], case["return_periods"])
+        assert int(r["hits"].sum()) == case["hits"]
+        assert int((r["ylt_pf"] > 0).sum()) == case["positive_trials"]
+        np.testing.assert_allclose(pml, case["pml"], rtol=1e-12)
+        np.testing.assert_allclose(tvar, case["tvar"], rtol=1e-12)
+        np.testing.assert_allclose(r["ylt_pf"][:16], case["ylt_head"], rtol=1e-12)
+        assert math.isclose(float(r["ylt_pf"].sum()), case["ylt_sum"], rel_tol=1e-12)

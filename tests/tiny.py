@@ -1,4 +1,7 @@
 """Small hand-made inputs shared by the oracle pins and the GPU parity tests."""
+import json
+from pathlib import Path
+
 import numpy as np
 
 from workloads import ELT, INF, YET, Layer, Portfolio
@@ -93,3 +96,30 @@ def random_tiny_case(rng, n_cat=12, n_layers=2, max_elts=3, max_occ=8, n_trials=
         layers.append(Layer(elts=elts, occ_retention=t[0], occ_limit=t[1],
                             agg_retention=t[2], agg_limit=t[3]))
     return yet, Portfolio(layers=layers, seed=int(rng.integers(0, 2**63)), su_enabled=su)
+
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
+def golden_worked_cases():
+    """The hand-worked fixture ``golden/worked_example.json``: yields (name,
+    yet, portfolio, expected) with expected holding ylt, gross, hits and the
+    flattened occurrence view of the single layer."""
+    with open(GOLDEN / "worked_example.json") as f:
+        g = json.load(f)
+    ev = g["events"]
+    lay = g["layer"]
+    for case in g["cases"]:
+        elts = []
+        for j, d in enumerate(g["elts"]):
+            share = case.get("share0", d["share"]) if j == 0 else d["share"]
+            elts.append(elt_from_dict(d["elt_id"], {ev[k]: v for k, v in d["rows"].items()},
+                                      d["retention"], d["limit"], share))
+        layer = Layer(elts=elts, occ_retention=lay["occ_retention"], occ_limit=lay["occ_limit"],
+                      agg_retention=lay["agg_retention"],
+                      agg_limit=case.get("agg_limit", lay["agg_limit"]))
+        pf = Portfolio(layers=[layer], seed=1, su_enabled=False)
+        yet = yet_from_lists([[ev[k] for k in t] for t in case["trials"]], g["catalogue"])
+        expect = {"ylt": case["ylt"], "gross": case["gross"], "hits": case["hits"],
+                  "occ_view": [d for t in case["occurrence_view"] for d in t]}
+        yield case["name"], yet, pf, expect
