@@ -73,3 +73,31 @@ def test_null_context_is_an_error_not_a_crash():
     assert lib.ara_run(None, None, None, None, None, None, None) == A.ARA_E_INVALID_ARG
     assert lib.ara_sync_status(None, None) == A.ARA_E_INVALID_ARG
     assert math.isfinite(0.0) and np is not None
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No fallback: without libara.so the binding refuses to run."""
+    code = ("import paper_1501_06326_amd.ara as A\n"
+            f"A.LIB_PATH = {str(tmp_path / 'absent' / 'libara.so')!r}\n"
+            "A._lib = None\n"
+            "try:\n"
+            "    A.lib()\n"
+            "except ImportError as e:\n"
+            "    print('refused:', e)\n"
+            "    raise SystemExit(0)\n"
+            "raise SystemExit(1)\n")
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "is missing" in r.stdout
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=ROOT, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
