@@ -51,120 +51,209 @@ struct KeyOf<double> {
     __device__ static double value(uint64_t k) { return __longlong_as_double((long long)k); }
 };
 
+// Return periods are selected together, up to kSelGroup per pass over the
+// YLT: every digit pass histograms all of them in one launch (periods whose
+// selections still share their prefix share one histogram) and one small
+// launch picks their digits, so a group costs the same launches whatever its
+// size.  Launch boundaries order the passes (a last-block-done handshake
+// would need a device-wide fence in every block, which costs more here).
+constexpr int kSelGroup = 8;
+
+struct SelGroup {
+    int64_t k[kSelGroup];
+};
+
+// Scratch layout of one group.
+struct SelScratch {
+    uint32_t *hist;                 // [kSelGroup][256]
+    SelState *st;                   // [kSelGroup]
+    double *psum;                   // [kSelGroup][kSumBlocks]
+    unsigned long long *pcnt;       // [kSelGroup][kSumBlocks]
+};
+
+__global__ __launch_bounds__(256) void k_init_state(SelScratch sc, SelGroup g, int m) {
+    for (int i = threadIdx.x; i < kSelGroup * 256; i += blockDim.x) sc.hist[i] = 0;
+    if ((int)threadIdx.x < m) {
+        SelState &s = sc.st[threadIdx.x];
+        s.prefix = 0;
+        s.mask = 0;
+        s.krem = g.k[threadIdx.x];
+        s.k = g.k[threadIdx.x];
+    }
+}
+
+// One digit of the selection for the m periods of a group.
 template <typename T>
-__global__ __launch_bounds__(256) void k_hist(const T *__restrict__ y, int64_t n,
-                                              const SelState *__restrict__ st, int shift,
-                                              uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+__global__ __launch_bounds__(256) void k_hist(const T *__restrict__ y, int64_t n, SelScratch sc,
+                                              int m, int shift) {
+    __shared__ uint32_t h[kSelGroup][256];
+    __shared__ uint64_t pre[kSelGroup], msk[kSelGroup];
+    __shared__ int rep[kSelGroup];
+    for (int i = threadIdx.x; i < kSelGroup * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    if (threadIdx.x == 0) {
+        for (int r = 0; r < m; ++r) {
+            pre[r] = sc.st[r].prefix;
+            msk[r] = sc.st[r].mask;
+            rep[r] = r;
+            for (int q = 0; q < r; ++q)
+                if (rep[q] == q && pre[q] == pre[r] && msk[q] == msk[r]) { rep[r] = q; break; }
+        }
+    }
     __syncthreads();
-    const uint64_t prefix = st->prefix, mask = st->mask;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t k = (uint64_t)KeyOf<T>::key(y[i]);
-        if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        for (int r = 0; r < m; ++r)
+            if (rep[r] == r && (k & msk[r]) == pre[r]) atomicAdd(&h[r][d], 1u);
     }
     __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
-}
-
-// One thread: pick the digit holding the k-th largest, clear the histogram.
-__global__ void k_select_digit(SelState *st, int shift, uint32_t *hist) {
-    int64_t krem = st->krem, cum = 0;
-    int pick = 0;
-    for (int b = 255; b >= 0; --b) {
-        const int64_t c = hist[b];
-        if (cum + c >= krem) { pick = b; break; }
-        cum += c;
+    for (int r = 0; r < m; ++r) {
+        const uint32_t c = h[rep[r]][threadIdx.x];
+        if (c) atomicAdd(&sc.hist[r * 256 + threadIdx.x], c);
     }
-    st->krem = krem - cum;
-    st->prefix |= (uint64_t)pick << shift;
-    st->mask |= (uint64_t)255 << shift;
-    for (int b = 0; b < 256; ++b) hist[b] = 0;
 }
 
-__global__ void k_init_state(SelState *st, int64_t k, uint32_t *hist) {
-    st->prefix = 0;
-    st->mask = 0;
-    st->krem = k;
-    st->k = k;
-    for (int b = 0; b < 256; ++b) hist[b] = 0;
+// One block of 256 threads: for each period, the digit holding its k-th
+// largest, from the suffix sums of its histogram (bin b counts the keys with
+// digit b; the k-th largest is in the bin where the suffix sum reaches krem);
+// then the histograms are cleared for the next digit.
+__global__ __launch_bounds__(256) void k_pick(SelScratch sc, int m, int shift) {
+    __shared__ uint64_t sfx[257];
+    for (int r = 0; r < m; ++r) {
+        const int64_t krem = sc.st[r].krem;
+        sfx[threadIdx.x] = sc.hist[r * 256 + threadIdx.x];
+        if (threadIdx.x == 0) sfx[256] = 0;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const uint64_t t = threadIdx.x + d < 256 ? sfx[threadIdx.x + d] : 0;
+            __syncthreads();
+            sfx[threadIdx.x] += t;
+            __syncthreads();
+        }
+        const int64_t here = (int64_t)sfx[threadIdx.x], above = (int64_t)sfx[threadIdx.x + 1];
+        __syncthreads();
+        if (here >= krem && above < krem) {
+            SelState &st = sc.st[r];
+            st.krem = krem - above;
+            st.prefix |= (uint64_t)threadIdx.x << shift;
+            st.mask |= (uint64_t)255 << shift;
+        }
+    }
+    for (int i = threadIdx.x; i < kSelGroup * 256; i += blockDim.x) sc.hist[i] = 0;
 }
 
+// TVaR of the group: per block and period, the FP64 sum and the count of the
+// losses strictly above the period's PML (a fixed tree per block).
 template <typename T>
-__global__ __launch_bounds__(256) void k_tail_sum(const T *__restrict__ y, int64_t n,
-                                                  const SelState *__restrict__ st,
-                                                  double *__restrict__ psum,
-                                                  unsigned long long *__restrict__ pcnt) {
+__global__ __launch_bounds__(256) void k_tail_sum(const T *__restrict__ y, int64_t n, SelScratch sc,
+                                                  int m) {
     __shared__ double s[256];
     __shared__ unsigned long long c[256];
-    const uint64_t thr = st->prefix;
-    double acc = 0.0;
-    unsigned long long cnt = 0;
+    __shared__ uint64_t thr[kSelGroup];
+    if ((int)threadIdx.x < m) thr[threadIdx.x] = sc.st[threadIdx.x].prefix;
+    __syncthreads();
+    double acc[kSelGroup];
+    unsigned long long cnt[kSelGroup];
+#pragma unroll
+    for (int r = 0; r < kSelGroup; ++r) {
+        acc[r] = 0.0;
+        cnt[r] = 0;
+    }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const T v = y[i];
-        if ((uint64_t)KeyOf<T>::key(v) > thr) {
-            acc += (double)v;
-            ++cnt;
+        const uint64_t k = (uint64_t)KeyOf<T>::key(v);
+#pragma unroll
+        for (int r = 0; r < kSelGroup; ++r) {
+            if (r < m && k > thr[r]) {
+                acc[r] += (double)v;
+                ++cnt[r];
+            }
         }
     }
-    s[threadIdx.x] = acc;
-    c[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int d = 128; d >= 1; d >>= 1) {
-        if ((int)threadIdx.x < d) {
-            s[threadIdx.x] += s[threadIdx.x + d];
-            c[threadIdx.x] += c[threadIdx.x + d];
+#pragma unroll
+    for (int r = 0; r < kSelGroup; ++r) {
+        if (r >= m) break;
+        s[threadIdx.x] = acc[r];
+        c[threadIdx.x] = cnt[r];
+        __syncthreads();
+        for (int d = 128; d >= 1; d >>= 1) {
+            if ((int)threadIdx.x < d) {
+                s[threadIdx.x] += s[threadIdx.x + d];
+                c[threadIdx.x] += c[threadIdx.x + d];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            sc.psum[r * kSumBlocks + blockIdx.x] = s[0];
+            sc.pcnt[r * kSumBlocks + blockIdx.x] = c[0];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        psum[blockIdx.x] = s[0];
-        pcnt[blockIdx.x] = c[0];
-    }
 }
 
+// One block: the nb blocks' partials of each period staged in LDS, added in
+// block order by one thread (the same order for every run), PML and TVaR out.
 template <typename T>
-__global__ void k_finish(const SelState *st, const double *psum, const unsigned long long *pcnt,
-                         int nb, double *out, int r, int n_rp) {
-    double s = 0.0;
-    unsigned long long c = 0;
-    for (int b = 0; b < nb; ++b) {
-        s += psum[b];
-        c += pcnt[b];
+__global__ __launch_bounds__(256) void k_tail_finish(SelScratch sc, int m, int nb,
+                                                     double *__restrict__ out, int r0, int n_rp) {
+    __shared__ double ps[kSumBlocks];
+    __shared__ unsigned long long pc[kSumBlocks];
+    for (int r = 0; r < m; ++r) {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            ps[b] = sc.psum[r * kSumBlocks + b];
+            pc[b] = sc.pcnt[r * kSumBlocks + b];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            unsigned long long q = 0;
+            for (int b = 0; b < nb; ++b) {
+                t += ps[b];
+                q += pc[b];
+            }
+            const double pml = KeyOf<T>::value(sc.st[r].prefix);
+            const int64_t k = sc.st[r].k;
+            out[r0 + r] = pml;
+            out[n_rp + r0 + r] = (t + (double)(k - (int64_t)q) * pml) / (double)k;
+        }
+        __syncthreads();
     }
-    const double pml = KeyOf<T>::value(st->prefix);
-    const int64_t k = st->k;
-    out[r] = pml;
-    out[n_rp + r] = (s + (double)(k - (int64_t)c) * pml) / (double)k;
 }
 
 size_t pml_scratch_bytes(int64_t n) {
     (void)n;
-    return 256 * sizeof(uint32_t) + 64 + kSumBlocks * (sizeof(double) + sizeof(unsigned long long)) +
-           256;
+    return kSelGroup * 256 * sizeof(uint32_t) + kSelGroup * sizeof(SelState) +
+           kSelGroup * kSumBlocks * (sizeof(double) + sizeof(unsigned long long));
 }
 
 template <typename T>
 static hipError_t run_select(const T *y, int64_t n, const int64_t *ks, int32_t n_rp, void *scratch,
                              double *d_out, hipStream_t s) {
     char *p = (char *)scratch;
-    uint32_t *hist = (uint32_t *)p;
-    SelState *st = (SelState *)(p + 256 * sizeof(uint32_t));
-    double *psum = (double *)(p + 256 * sizeof(uint32_t) + 64);
-    unsigned long long *pcnt = (unsigned long long *)(psum + kSumBlocks);
+    SelScratch sc;
+    sc.hist = (uint32_t *)p;
+    p += kSelGroup * 256 * sizeof(uint32_t);
+    sc.st = (SelState *)p;
+    p += kSelGroup * sizeof(SelState);
+    sc.psum = (double *)p;
+    p += kSelGroup * kSumBlocks * sizeof(double);
+    sc.pcnt = (unsigned long long *)p;
     int64_t gb = (n + 255) / 256;
     const int g = (int)(gb < 1024 ? (gb < 1 ? 1 : gb) : 1024);
     const int gs = (int)(gb < kSumBlocks ? (gb < 1 ? 1 : gb) : kSumBlocks);
-    for (int r = 0; r < n_rp; ++r) {
-        hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, ks[r], hist);
+    for (int r0 = 0; r0 < n_rp; r0 += kSelGroup) {
+        const int m = n_rp - r0 < kSelGroup ? n_rp - r0 : kSelGroup;
+        SelGroup grp;
+        for (int r = 0; r < kSelGroup; ++r) grp.k[r] = r < m ? ks[r0 + r] : 1;
+        hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, s, sc, grp, m);
         for (int shift = KeyOf<T>::bits - 8; shift >= 0; shift -= 8) {
-            hipLaunchKernelGGL(k_hist<T>, dim3(g), dim3(256), 0, s, y, n, st, shift, hist);
-            hipLaunchKernelGGL(k_select_digit, dim3(1), dim3(1), 0, s, st, shift, hist);
+            hipLaunchKernelGGL(k_hist<T>, dim3(g), dim3(256), 0, s, y, n, sc, m, shift);
+            hipLaunchKernelGGL(k_pick, dim3(1), dim3(256), 0, s, sc, m, shift);
         }
-        hipLaunchKernelGGL(k_tail_sum<T>, dim3(gs), dim3(256), 0, s, y, n, st, psum, pcnt);
-        hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(1), 0, s, st, psum, pcnt, gs, d_out, r, n_rp);
+        hipLaunchKernelGGL(k_tail_sum<T>, dim3(gs), dim3(256), 0, s, y, n, sc, m);
+        hipLaunchKernelGGL(k_tail_finish<T>, dim3(1), dim3(256), 0, s, sc, m, gs, d_out, r0, n_rp);
     }
     return hipGetLastError();
 }
