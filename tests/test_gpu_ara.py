@@ -254,6 +254,36 @@ def test_pml_tvar_on_same_ylt(ara):
             assert abs(tvar[r_] - math.fsum(s[:k]) / k) <= 1e-12 * abs(tvar[r_]) + 1e-300
 
 
+def test_pml_tvar_many_return_periods(ara):
+    """Return periods are selected in groups of up to eight: 19 periods (three
+    groups) with duplicates, periods whose k-th largest values share their
+    leading digits, k = 1 and k = N, negative zeros, two calls in a row."""
+    rng = np.random.default_rng(11)
+    n = 200_003
+    v = rng.lognormal(14, 1.5, size=n).astype(np.float32)
+    v[rng.random(n) < 0.4] = 0
+    v[rng.random(n) < 0.05] = -0.0
+    v[100:200] = v[99]                              # a run of ties
+    t = torch.from_numpy(v).cuda()
+    rps = [100.0, 101.0, 99.5, 250.0, 250.0, 1.0, 1.5, 2.0, 1e9, 3.0, 10.0, 20.0, 50.0, 200.0,
+           500.0, 1000.0, 5000.0, 100.0, 1.0001]
+    s = np.sort(v.astype(np.float64))[::-1]
+    for call in range(2):
+        say("pml many return periods, call", call)
+        pml, tvar = ara.pml_tvar(t, rps)
+        for r_, rp in enumerate(rps):
+            k = max(1, int(math.floor(n / rp)))
+            assert pml[r_] == s[k - 1], (rp, pml[r_], s[k - 1])
+            assert abs(tvar[r_] - math.fsum(s[:k]) / k) <= 1e-12 * abs(tvar[r_]) + 1e-300, rp
+        # a shorter YLT through the same scratch
+        pml2, tvar2 = ara.pml_tvar(t[:1000], [7.0, 1.0, 1000.0])
+        s2 = np.sort(v[:1000].astype(np.float64))[::-1]
+        for r_, rp in enumerate([7.0, 1.0, 1000.0]):
+            k = max(1, int(math.floor(1000 / rp)))
+            assert pml2[r_] == s2[k - 1]
+            assert abs(tvar2[r_] - math.fsum(s2[:k]) / k) <= 1e-12 * abs(tvar2[r_]) + 1e-300
+
+
 def test_input_errors(ara):
     from paper_1501_06326_amd.ara import (ARA_E_BAD_ELT_ROW, ARA_E_EVENT_ID_RANGE,
                                           ARA_E_OFFSETS_NOT_MONOTONE, ARA_E_TIMES_UNSORTED,
