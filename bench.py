@@ -25,6 +25,10 @@ Two further modes print their own JSON line:
                   layers, 2-32 ELTs per layer, trial ranges of 1e4-1e6 trials):
                   p50 / p99 latency and throughput at several offered loads,
                   against a one-at-a-time server with the measured service times.
+  --mode views    the outputs either side of the YLT on the full shape: ara_run
+                  with the per-occurrence view (secondary uncertainty on and
+                  off; 1e9 FP32 increments written) and ara_ep_curve on the
+                  1,000,000-entry YLT.
 """
 import argparse
 import json
@@ -118,7 +122,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one elementwise kernel that reads and writes 1 GiB (a "
                          "known-size kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--mode", choices=["step", "batched", "served", "precision"], default="step")
+    ap.add_argument("--mode", choices=["step", "batched", "served", "precision", "views"],
+                    default="step")
     ap.add_argument("--oracle-trials", type=int, default=3000, help="precision mode")
     ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
     ap.add_argument("--graph", action="store_true", help="batched mode: also time a graph replay")
@@ -138,6 +143,8 @@ def main():
         return bench_served(args)
     if args.mode == "precision":
         return bench_precision(args)
+    if args.mode == "views":
+        return bench_views(args)
 
     import torch
     from paper_1501_06326_amd import Ara, evaluations
@@ -459,6 +466,69 @@ def bench_precision(args):
                          "oracle_trials": m, "return_periods": rps,
                          "evaluations_per_run": evals},
               "modes": modes}
+    print(json.dumps(result), flush=True)
+    ara.close()
+
+
+def bench_views(args):
+    """The occurrence view (the per-occurrence increments of the aggregate
+    loss, in stored order) and the exceedance-probability curve, on the
+    full-shape workload, timed with HIP events on the launch stream."""
+    import torch
+    from paper_1501_06326_amd import Ara
+    from workloads import config_full, full_portfolio
+
+    w = config_full(n_trials=args.trials, n_catalogue=args.catalogue)
+    yet, pf_su = w.yet, w.portfolio
+    pf_pu = full_portfolio(su=False, n_catalogue=args.catalogue)
+    ara = Ara(0)
+    dev = ara.device
+    off = torch.from_numpy(yet.offsets).to(dev)
+    ev = torch.from_numpy(yet.event_ids).to(dev)
+    tm = torch.from_numpy(yet.times).to(dev) if yet.times is not None else None
+    y = ara.load_yet(yet, device_arrays=(off, ev, tm))
+    stream = torch.cuda.current_stream()
+    n_occ = int(yet.n_occ)
+    out = {}
+
+    def timed(fn, reps):
+        fn()                                               # warmup and status check
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = fn(sync=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            del r
+        return float(np.mean(ms))
+
+    for name, pf in (("su", pf_su), ("pu", pf_pu)):
+        p = ara.load_portfolio(pf, yet.n_catalogue)
+        ms = timed(lambda sync=True: ara.run(y, p, occ_view=True, sync=sync), args.steps)
+        # written: one FP32 increment per occurrence (the binding's zero fill of
+        # that buffer is inside the timed region); read: the event ids
+        out[name] = {"ms_per_run": ms, "occurrences_per_s": n_occ / (ms / 1e3),
+                     "view_bytes": 4 * n_occ,
+                     "view_gb_per_s": 4 * n_occ / (ms / 1e3) / 1e9}
+        log(f"occurrence view ({name}): {ms:.2f} ms for {n_occ} occurrences")
+        ara.free_portfolio(p)
+        torch.cuda.empty_cache()
+
+    p = ara.load_portfolio(pf_su, yet.n_catalogue)
+    ylt = ara.run(y, p)["ylt_pf"]
+    ms = timed(lambda sync=True: ara.ep_curve(ylt), args.steps)
+    out["ep_curve"] = {"ms_per_call": ms, "entries": int(ylt.numel()),
+                       "entries_per_s": ylt.numel() / (ms / 1e3)}
+    log(f"EP curve: {ms:.3f} ms for {ylt.numel()} entries")
+    result = {"metric": "occurrence view and exceedance-probability curve",
+              "n_gpus": 1, "steps": args.steps, "dtype": "f32 (FP64 running means)",
+              "data": "synthetic (seeded numpy generator; lognormal ELT means)",
+              "config": {"workload": w.name, "trials": yet.n_trials, "occurrences": n_occ,
+                         "catalogue": yet.n_catalogue, "layers": 1, "elts": 16},
+              **out}
     print(json.dumps(result), flush=True)
     ara.close()
 

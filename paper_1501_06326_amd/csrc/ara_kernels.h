@@ -113,6 +113,9 @@ hipError_t launch_build_sparse(const float *otab, int32_t n_cat, uint32_t *bits,
 hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s);
 hipError_t launch_batch(const BatchArgs &B, int mode, bool f64out, int grid, int redo_grid,
                         hipStream_t s);
+// exclusive prefix sum of p[0, n) in place (one block; also used by the
+// exceedance-curve sort for its digit counts)
+hipError_t launch_scan_excl_u32(uint32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out,
                                hipStream_t s);
 hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, const double *z,

@@ -651,7 +651,7 @@ struct SuArgs {
     Status *status;
     int32_t *redo;            // trials (relative index) handed to the FP64-capable pass
     uint32_t *redo_count;
-    void *occ_view;           // occurrence view, written by the DIAG instantiations only
+    void *occ_view;           // occurrence view, written by the DIAG and OCC instantiations
     int64_t occ_stride;
 };
 
@@ -702,7 +702,7 @@ __device__ __forceinline__ void hit_z(uint32_t meta, uint32_t jI, uint32_t jC, T
 // quantile (tail band, shape outside the FP32 domain, FP32 non-convergence)
 // abandons the trial, which is then queued for the REDO = true pass, where
 // such hits take the FP64 path in place.  Returns true when abandoned.
-template <int MODE, bool F64OUT, bool DIAG, bool REDO>
+template <int MODE, bool F64OUT, bool DIAG, bool REDO, bool OCC = false>
 __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys, int64_t t,
                                          float *X, uint2 *Q, EltDev *El) {
     const int lane = threadIdx.x;
@@ -889,7 +889,7 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
             __syncthreads();
             for (int i = lane; i < segn; i += kWave)
                 acc.add(clampf_terms(X[i], L.occ_r, L.occ_l));
-            if (DIAG && A.occ_view) {
+            if ((DIAG || OCC) && A.occ_view) {
                 const int64_t pos0 = o0 - A.off[A.trial_begin] + seg;
                 for (int c = 0; c < segn; c += kWave) {
                     const int i = c + lane;
@@ -931,28 +931,31 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
     return false;
 }
 
-// Main pass: one wavefront (block) per trial.
-template <int MODE, bool F64OUT, bool DIAG>
+// Main pass: one wavefront (block) per trial.  DIAG: every row visited, hit
+// counts and checksums (and the occurrence view when asked for); OCC: the
+// lean pass that also writes the occurrence view (its per-occurrence sums
+// are those of the DIAG pass: the rows it skips add +0).
+template <int MODE, bool F64OUT, bool DIAG, bool OCC = false>
 __global__ __launch_bounds__(64) ARA_SU_OCCUPANCY void k_ara_su(SuArgs A, PhiloxKeys keys) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
     __shared__ EltDev El[kEltLds];
     const int64_t t = blockIdx.x;
     if (t >= A.trial_count) return;
-    if (su_trial<MODE, F64OUT, DIAG, false>(A, keys, t, X, Q, El) && threadIdx.x == 0)
+    if (su_trial<MODE, F64OUT, DIAG, false, OCC>(A, keys, t, X, Q, El) && threadIdx.x == 0)
         A.redo[atomicAdd(A.redo_count, 1u)] = (int32_t)t;
 }
 
 // FP64-capable pass over the trials the main pass handed over; the count is
 // read on the device, so no host round trip is needed between the passes.
-template <int MODE, bool F64OUT, bool DIAG>
+template <int MODE, bool F64OUT, bool DIAG, bool OCC = false>
 __global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
     __shared__ EltDev El[kEltLds];
     const uint32_t n = *A.redo_count;
     for (uint32_t r = blockIdx.x; r < n; r += gridDim.x)
-        su_trial<MODE, F64OUT, DIAG, true>(A, keys, (int64_t)A.redo[r], X, Q, El);
+        su_trial<MODE, F64OUT, DIAG, true, OCC>(A, keys, (int64_t)A.redo[r], X, Q, El);
 }
 
 // ---------------------------------------------------------------------------
@@ -1260,13 +1263,22 @@ static hipError_t su_dispatch2(const SuLaunch &p, hipStream_t s) {
     // a kernel, not hipMemsetAsync, so the sequence can be captured in a graph
     hipLaunchKernelGGL(k_reset_u32, dim3(1), dim3(1), 0, s, p.redo_count);
     const dim3 g((unsigned)p.trial_count), gr((unsigned)p.redo_grid);
-    if (p.hits || p.hit_chk || p.occ_view) {
+    if (p.hits || p.hit_chk) {
         hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, true>), g, dim3(64), 0, s, A, keys);
         hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, true>), gr, dim3(64), 0, s, A, keys);
+    } else if (p.occ_view) {
+        hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, false, true>), g, dim3(64), 0, s, A, keys);
+        hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, false, true>), gr, dim3(64), 0, s, A, keys);
     } else {
         hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, false>), g, dim3(64), 0, s, A, keys);
         hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, false>), gr, dim3(64), 0, s, A, keys);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_excl_u32(uint32_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_excl_u32, dim3(1), dim3(1024), 0, s, p, n);
     return hipGetLastError();
 }
 

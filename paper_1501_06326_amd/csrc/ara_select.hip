@@ -286,30 +286,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K *__restrict_
     counts[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of c[0, m) in place: one block, a serial chunk per thread.
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ c, int64_t m) {
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t chunk = (m + 1023) / 1024;
-    const int64_t b = (int64_t)tid * chunk, e = (b + chunk) < m ? (b + chunk) : m;
-    uint32_t sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += c[i];
-    part[tid] = sum;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const uint32_t v = tid >= d ? part[tid - d] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint32_t run = tid ? part[tid - 1] : 0u;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t v = c[i];
-        c[i] = run;
-        run += v;
-    }
-}
-
 // Stable scatter of one digit: the block's keys in kSortIpt rounds of 256 (in
 // index order); in a round each wavefront finds the lanes sharing a lane's
 // digit with eight ballots, the lowest of them records the count, and a key
@@ -388,12 +364,29 @@ __global__ __launch_bounds__(kSortThreads) void k_tm_partial(const T *__restrict
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-__global__ void k_tm_scan(double *__restrict__ part, int nb) {
-    double run = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        const double v = part[b];
-        part[b] = run;
-        run += v;
+// Exclusive scan of the block sums in block order (one thread adds, so the
+// order is fixed); tiles of them are staged through LDS by the whole block.
+__global__ __launch_bounds__(kSortThreads) void k_tm_scan(double *__restrict__ part, int nb) {
+    constexpr int kT = kSortThreads * 8;
+    __shared__ double t[kT];
+    __shared__ double carry;
+    if (threadIdx.x == 0) carry = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += kT) {
+        const int m = nb - b0 < kT ? nb - b0 : kT;
+        for (int i = threadIdx.x; i < m; i += blockDim.x) t[i] = part[b0 + i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double run = carry;
+            for (int i = 0; i < m; ++i) {
+                const double v = t[i];
+                t[i] = run;
+                run += v;
+            }
+            carry = run;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < m; i += blockDim.x) part[b0 + i] = t[i];
+        __syncthreads();
     }
 }
 
@@ -451,7 +444,7 @@ static hipError_t run_ep(const T *y, int64_t n, T *sorted, double *tail_mean, vo
     for (int shift = 0; shift < KeyOf<T>::bits; shift += 8) {   // an even number of passes
         hipLaunchKernelGGL((k_sort_hist<K>), dim3(nb), dim3(kSortThreads), 0, s, a, n, shift,
                            counts, nb);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, (int64_t)256 * nb);
+        launch_scan_excl_u32(counts, (int64_t)256 * nb, s);
         hipLaunchKernelGGL((k_sort_scatter<K>), dim3(nb), dim3(kSortThreads), 0, s, a, b, n,
                            shift, counts, nb);
         K *t = a;
@@ -461,7 +454,7 @@ static hipError_t run_ep(const T *y, int64_t n, T *sorted, double *tail_mean, vo
     hipLaunchKernelGGL((k_sort_values<T>), dim3(g), dim3(256), 0, s, keys, n);
     if (tail_mean) {
         hipLaunchKernelGGL((k_tm_partial<T>), dim3(nb), dim3(kSortThreads), 0, s, sorted, n, part);
-        hipLaunchKernelGGL(k_tm_scan, dim3(1), dim3(1), 0, s, part, nb);
+        hipLaunchKernelGGL(k_tm_scan, dim3(1), dim3(kSortThreads), 0, s, part, nb);
         hipLaunchKernelGGL((k_tm_final<T>), dim3(nb), dim3(kSortThreads), 0, s, sorted, n, part,
                            tail_mean);
     }

@@ -65,6 +65,27 @@ def test_occurrence_view_vs_oracle(ara, su, sum_mode, dtype):
     ara.free_yet(y)
 
 
+@pytest.mark.parametrize("corr", [False, True])
+def test_occurrence_view_lean_equals_diagnostic(ara, corr):
+    """Without hit counts the view comes from the lean pass (only the rows that
+    can pay are visited); with them, from the diagnostic pass (every row).
+    The rows the lean pass skips add +0, so the two views are bit-identical;
+    the correlated case sends trials through the FP64-capable second pass."""
+    w = config_small(corr=corr, n_trials=3000)
+    tb, tc = 100, 2700
+    say("occ view lean vs diagnostic, corr", corr)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    lean = ara.run(y, p, trial_begin=tb, trial_count=tc, occ_view=True)
+    diag = ara.run(y, p, trial_begin=tb, trial_count=tc, occ_view=True, diagnostics=True)
+    assert torch.equal(lean["occ_view"], diag["occ_view"])
+    assert torch.equal(lean["ylt"], diag["ylt"])
+    plain = ara.run(y, p, trial_begin=tb, trial_count=tc)
+    assert torch.equal(lean["ylt"], plain["ylt"])
+    ara.free_portfolio(p)
+    ara.free_yet(y)
+
+
 def test_occurrence_view_stride_too_small(ara):
     from paper_1501_06326_amd.ara import ARA_E_WORKSPACE_TOO_SMALL, AraError
     w = config_small(n_trials=200)
