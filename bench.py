@@ -60,9 +60,9 @@ VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "588"))
 # 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
 # the counters were taken with; null otherwise.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "310c9cc7fefd41be89db48b745c144442e0a903d0e1b94345936306f666865b7",
-    "su_main_bytes": 27.243e9 + 0.1070e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0881e9 + 0.0304e9,        # k_ara_pu: fetch + write, 1M trials
+    "sources_sha256": "464e2f0a97e4bafc761f6e2a70d3dae32408b1998834f3d96bbbf1706ddaaebc",
+    "su_main_bytes": 27.250e9 + 0.1070e9,   # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0880e9 + 0.0305e9,        # k_ara_pu: fetch + write, 1M trials
 }
 
 
