@@ -475,16 +475,35 @@ enum { TAB_GLOBAL = 0, TAB_LDS_DENSE = 1, TAB_LDS_SPARSE = 2 };
 // aggregate terms give A = min(max(S - AggR, 0), AggL) (carried in *ca), and
 // the lane's increment A - A_prev is written at pos when valid.  Every lane
 // of the wave calls this (the scan reads all of them).
+// A DPP move of an FP64 value (both 32-bit halves with the same control);
+// lanes that receive nothing read 0.0.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xf, BOUND);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xf, BOUND);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 template <bool F64OUT>
 __device__ __forceinline__ void occ_chunk(double o, bool valid, int64_t pos, int layer,
                                           void *view, int64_t stride, float agg_r, float agg_l,
                                           double *cs, double *ca, Status *st, int64_t trial) {
     const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double v = __shfl_up(o, d, 64);
-        if (lane >= d) o += v;
-    }
+    // inclusive FP64 prefix sum over the wavefront, laid out as in wave_excl_scan
+    o += dpp_f64<0x111, 0xf, true>(o);    // row_shr:1
+    o += dpp_f64<0x112, 0xf, true>(o);    // row_shr:2
+    o += dpp_f64<0x114, 0xf, true>(o);    // row_shr:4
+    o += dpp_f64<0x118, 0xf, true>(o);    // row_shr:8
+    o += dpp_f64<0x142, 0xa, false>(o);   // row_bcast:15
+    o += dpp_f64<0x143, 0xc, false>(o);   // row_bcast:31
     const double S = *cs + o;
     const double A = clampd_terms(S, (double)agg_r, (double)agg_l);
     double Ap = __shfl_up(A, 1, 64);
@@ -498,8 +517,8 @@ __device__ __forceinline__ void occ_chunk(double o, bool valid, int64_t pos, int
             report(st, ARA_E_WORKSPACE_TOO_SMALL, trial, pos, stride);
         }
     }
-    *cs = __shfl(S, 63, 64);
-    *ca = __shfl(A, 63, 64);
+    *cs = readlane_f64(S, 63);
+    *ca = readlane_f64(A, 63);
 }
 
 // Occurrence view of a primary-uncertainty layer (one wavefront per trial):
