@@ -521,10 +521,45 @@ __device__ __forceinline__ void occ_chunk(double o, bool valid, int64_t pos, int
     *ca = readlane_f64(A, 63);
 }
 
+// The layer's per-event occurrence-loss table, staged by the whole block in
+// LDS (dense, or sparse: a bit per event, the rank of each 32-event word and
+// the non-zero values) or read from global memory (catalogues too large).
+template <int TAB>
+__device__ __forceinline__ void pu_stage_table(const PuArgs &P, uint32_t *sm) {
+    const int32_t nw = (P.n_cat + 31) >> 5;
+    if (TAB == TAB_LDS_DENSE) {
+        float *tab = (float *)sm;
+        for (int i = threadIdx.x; i < P.n_cat; i += blockDim.x) tab[i] = P.otab[i];
+    } else if (TAB == TAB_LDS_SPARSE) {
+        uint32_t *bits = sm, *rank = sm + nw;
+        float *vals = (float *)(sm + 2 * nw + 1);
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) bits[i] = P.sp_bits[i];
+        for (int i = threadIdx.x; i <= nw; i += blockDim.x) rank[i] = P.sp_rank[i];
+        for (int i = threadIdx.x; i < P.nnz; i += blockDim.x) vals[i] = P.sp_vals[i];
+    }
+    if (TAB != TAB_GLOBAL) __syncthreads();
+}
+
+template <int TAB>
+__device__ __forceinline__ float pu_look(const PuArgs &P, const uint32_t *sm, int32_t E) {
+    if (TAB == TAB_GLOBAL) return P.otab[E];
+    if (TAB == TAB_LDS_DENSE) return ((const float *)sm)[E];
+    const int32_t nw = (P.n_cat + 31) >> 5;
+    const uint32_t w = sm[E >> 5];
+    const uint32_t m = 1u << (E & 31);
+    return (w & m) ? ((const float *)(sm + 2 * nw + 1))[sm[nw + (E >> 5)] + __popc(w & (m - 1u))]
+                   : 0.0f;
+}
+
 // Occurrence view of a primary-uncertainty layer (one wavefront per trial):
-// the per-event occurrence losses of the layer's table, in stored order.
-template <bool F64OUT>
-__global__ __launch_bounds__(256) void k_pu_occ_view(PuArgs P) {
+// the per-event occurrence losses of the layer's table, in stored order.  The
+// table sits in LDS as for the YLT pass (16-wavefront blocks sharing a copy):
+// read from global memory, its 64 scattered lookups per chunk load the L2
+// with a request per lane.
+template <bool F64OUT, int TAB>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pu_occ_view(PuArgs P) {
+    extern __shared__ uint32_t sm[];
+    pu_stage_table<TAB>(P, sm);
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int64_t nwv = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -535,7 +570,7 @@ __global__ __launch_bounds__(256) void k_pu_occ_view(PuArgs P) {
         for (int64_t c = a; c < b; c += 64) {
             const int64_t j = c + lane;
             const bool valid = j < b;
-            const double o = valid ? (double)P.otab[P.ev[j]] : 0.0;
+            const double o = valid ? (double)pu_look<TAB>(P, sm, P.ev[j]) : 0.0;
             occ_chunk<F64OUT>(o, valid, j - base, P.layer, P.occ_view, P.occ_stride, P.agg_r,
                               P.agg_l, &cs, &ca, P.status, P.trial_begin + t);
         }
@@ -551,25 +586,8 @@ __global__ __launch_bounds__(256) void k_pu_occ_view(PuArgs P) {
 template <int MODE, bool F64OUT, int TAB>
 __device__ __forceinline__ void pu_trials(const PuArgs &P) {
     extern __shared__ uint32_t sm[];
-    const int32_t nw = (P.n_cat + 31) >> 5;
-    float *tab = (float *)sm;
-    uint32_t *bits = sm, *rank = sm + nw;
-    float *vals = (float *)(sm + 2 * nw + 1);
-    if (TAB == TAB_LDS_DENSE) {
-        for (int i = threadIdx.x; i < P.n_cat; i += blockDim.x) tab[i] = P.otab[i];
-    } else if (TAB == TAB_LDS_SPARSE) {
-        for (int i = threadIdx.x; i < nw; i += blockDim.x) bits[i] = P.sp_bits[i];
-        for (int i = threadIdx.x; i <= nw; i += blockDim.x) rank[i] = P.sp_rank[i];
-        for (int i = threadIdx.x; i < P.nnz; i += blockDim.x) vals[i] = P.sp_vals[i];
-    }
-    if (TAB != TAB_GLOBAL) __syncthreads();
-    auto look = [&](int32_t E) -> float {
-        if (TAB == TAB_GLOBAL) return P.otab[E];
-        if (TAB == TAB_LDS_DENSE) return tab[E];
-        const uint32_t w = bits[E >> 5];
-        const uint32_t m = 1u << (E & 31);
-        return (w & m) ? vals[rank[E >> 5] + __popc(w & (m - 1u))] : 0.0f;
-    };
+    pu_stage_table<TAB>(P, sm);
+    auto look = [&](int32_t E) -> float { return pu_look<TAB>(P, sm, E); };
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int64_t nwv = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -1238,13 +1256,20 @@ static hipError_t pu_dispatch(const PuLaunch &p, hipStream_t s) {
     A.nnz = p.nnz; A.n_cat = p.n_cat; A.agg_r = p.agg_r; A.agg_l = p.agg_l; A.layer = p.layer;
     A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf; A.accumulate_pf = p.accumulate_pf;
     A.occ_view = p.occ_view; A.occ_stride = p.occ_stride; A.status = p.status;
-    if (p.occ_view)
-        hipLaunchKernelGGL((k_pu_occ_view<F64OUT>), dim3(p.grid * 4), dim3(256), 0, s, A);
     const size_t nw = ((size_t)p.n_cat + 31) / 32;
     const size_t dense = (size_t)p.n_cat * sizeof(float);
     const size_t sparse = (2 * nw + 1 + (size_t)p.nnz) * sizeof(uint32_t);
     // p.grid counts blocks of 16 wavefronts (two per CU at most)
     const dim3 g(p.grid), b(1024);
+    if (p.occ_view) {
+        if (dense <= 32 * 1024)
+            hipLaunchKernelGGL((k_pu_occ_view<F64OUT, TAB_LDS_DENSE>), g, b, dense, s, A);
+        else if (sparse <= 60 * 1024)
+            hipLaunchKernelGGL((k_pu_occ_view<F64OUT, TAB_LDS_SPARSE>), g, b, sparse, s, A);
+        else
+            hipLaunchKernelGGL((k_pu_occ_view<F64OUT, TAB_GLOBAL>), dim3(p.grid * 4), dim3(256), 0,
+                               s, A);
+    }
     if (dense <= 32 * 1024) {
         hipLaunchKernelGGL((k_ara_pu<MODE, F64OUT, TAB_LDS_DENSE>), g, b, dense, s, A);
     } else if (sparse <= 60 * 1024) {

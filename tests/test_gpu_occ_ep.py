@@ -86,6 +86,26 @@ def test_occurrence_view_lean_equals_diagnostic(ara, corr):
     ara.free_yet(y)
 
 
+@pytest.mark.parametrize("n_catalogue", [1_000_000])
+def test_occurrence_view_table_layouts(ara, n_catalogue):
+    """Without secondary uncertainty the view reads the per-event table from
+    LDS, dense (the golden worked example) or sparse (the small workload,
+    above), or from global memory when it is too large for LDS (here)."""
+    from workloads import config_full
+    w = config_full(n_trials=300, with_times=False, su=False, n_catalogue=n_catalogue)
+    say("occ view table layout, catalogue", n_catalogue, w.yet.n_occ)
+    ref = oracle.run_ara(w.yet, w.portfolio, occ_view=True)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(w.portfolio, w.yet.n_catalogue)
+    r = ara.run(y, p, occ_view=True)
+    d = r["occ_view"].double().cpu().numpy()
+    G = per_occurrence_gross(w.yet, 0, w.yet.n_trials, ref["gross"])
+    err = np.abs(d - ref["occ_view"])
+    assert np.all(err <= 2 * (1e-5 * G + 1e-3)), err.max()
+    ara.free_portfolio(p)
+    ara.free_yet(y)
+
+
 def test_occurrence_view_stride_too_small(ara):
     from paper_1501_06326_amd.ara import ARA_E_WORKSPACE_TOO_SMALL, AraError
     w = config_small(n_trials=200)
