@@ -60,9 +60,9 @@ VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "588"))
 # 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
 # the counters were taken with; null otherwise.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "a7b5d6c25fcf36c0ba5e330ce5c6d18395e7db5faa69ee398ce271de6f83cbbd",
-    "su_main_bytes": 27.252e9 + 0.1068e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0880e9 + 0.0306e9,        # k_ara_pu: fetch + write, 1M trials
+    "sources_sha256": "df1a58214dcef546b09d85b04bbef076f1424330e724b560a6bca46d43d45534",
+    "su_main_bytes": 27.244e9 + 0.1070e9,   # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0884e9 + 0.0306e9,        # k_ara_pu: fetch + write, 1M trials
 }
 
 
