@@ -23,6 +23,9 @@
 //        k_ara_su_redo, which runs it again with the FP64 path in place.
 //      - k_ara_batch / k_ara_batch_items: the same trial code over
 //        (portfolio, trial tile) work items of many portfolios at once.
+//      - the occurrence view (per-occurrence increments of the aggregate
+//        terms): the OCC instantiation of k_ara_su, or k_pu_occ_view without
+//        secondary uncertainty, both through occ_chunk's wavefront scan.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
