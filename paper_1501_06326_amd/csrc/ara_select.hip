@@ -260,7 +260,7 @@ static hipError_t run_select(const T *y, int64_t n, const int64_t *ks, int32_t n
 
 // ---- exceedance-probability curve ------------------------------------------
 constexpr int kSortThreads = 256;
-constexpr int kSortIpt = 8;
+constexpr int kSortIpt = 16;
 constexpr int kSortTile = kSortThreads * kSortIpt;   // keys per block and pass
 
 template <typename T>
