@@ -254,25 +254,27 @@ def test_pml_tvar_on_same_ylt(ara):
             assert abs(tvar[r_] - math.fsum(s[:k]) / k) <= 1e-12 * abs(tvar[r_]) + 1e-300
 
 
-def test_pml_tvar_many_return_periods(ara):
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_pml_tvar_many_return_periods(ara, dt):
     """Return periods are selected in groups of up to eight: 19 periods (three
     groups) with duplicates, periods whose k-th largest values share their
-    leading digits, k = 1 and k = N, negative zeros, two calls in a row."""
+    leading digits, k = 1, k = N (and a period below 1, whose k is clamped to
+    N), negative zeros, two calls in a row; FP32 and FP64 losses."""
     rng = np.random.default_rng(11)
     n = 200_003
-    v = rng.lognormal(14, 1.5, size=n).astype(np.float32)
+    v = rng.lognormal(14, 1.5, size=n).astype(dt)
     v[rng.random(n) < 0.4] = 0
     v[rng.random(n) < 0.05] = -0.0
     v[100:200] = v[99]                              # a run of ties
     t = torch.from_numpy(v).cuda()
     rps = [100.0, 101.0, 99.5, 250.0, 250.0, 1.0, 1.5, 2.0, 1e9, 3.0, 10.0, 20.0, 50.0, 200.0,
-           500.0, 1000.0, 5000.0, 100.0, 1.0001]
+           500.0, 1000.0, 5000.0, 0.5, 1.0001]
     s = np.sort(v.astype(np.float64))[::-1]
     for call in range(2):
-        say("pml many return periods, call", call)
+        say("pml many return periods", dt.__name__, "call", call)
         pml, tvar = ara.pml_tvar(t, rps)
         for r_, rp in enumerate(rps):
-            k = max(1, int(math.floor(n / rp)))
+            k = min(n, max(1, int(math.floor(n / rp))))
             assert pml[r_] == s[k - 1], (rp, pml[r_], s[k - 1])
             assert abs(tvar[r_] - math.fsum(s[:k]) / k) <= 1e-12 * abs(tvar[r_]) + 1e-300, rp
         # a shorter YLT through the same scratch
