@@ -158,7 +158,8 @@ const char *ara_last_error(const ara_context *ctx);
 
 /* ---- Year Event Table (section 2.1 (i)) ---------------------------------
  * CSR by trial: trial t holds occurrences [d_trial_offsets[t],
- * d_trial_offsets[t+1]) of d_event_ids (int32, 0-based catalogue ids) and
+ * d_trial_offsets[t+1]) of d_event_ids (int32, 0-based catalogue ids; may be
+ * NULL when d_trial_offsets[n_trials] == 0, a YET of empty trials) and
  * d_times (float32 time stamps, may be NULL).  The arrays are borrowed and
  * must stay alive and unchanged until ara_free_yet.  Validates on the device
  * (ids in range, offsets[0] == 0 and non-decreasing, times non-decreasing

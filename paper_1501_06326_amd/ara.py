@@ -557,7 +557,7 @@ class Ara:
         ov = None
         if occ_view:
             n_occ = int(y.offsets_host[trial_begin + trial_count] - y.offsets_host[trial_begin])
-            stride = n_occ if occ_view_stride is None else int(occ_view_stride)
+            stride = max(1, n_occ) if occ_view_stride is None else int(occ_view_stride)
             ov = t.zeros((p.n_layers, max(1, stride)), dtype=dt, device=self.device)
         o = ara_run_opts(trial_begin=int(trial_begin), trial_count=int(trial_count),
                          sum_mode=SUM_MODES[sum_mode],

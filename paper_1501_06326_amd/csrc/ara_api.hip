@@ -252,16 +252,22 @@ ara_status ara_load_yet(ara_context *ctx, int64_t n_trials, int32_t n_catalogue,
                         const float *d_times, void *stream, ara_yet **out) {
     if (!ctx) return ARA_E_INVALID_ARG;
     if (!out || n_trials < 0 || n_catalogue <= 0 || !d_trial_offsets ||
-        (n_trials > 0 && !d_event_ids) || n_trials > (int64_t)0xffffffff)
+        n_trials > (int64_t)0xffffffff)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_load_yet: bad arguments");
     *out = nullptr;
     hipStream_t s = (hipStream_t)stream;
     ARA_HIP(ctx, hipSetDevice(ctx->device));
     ARA_HIP(ctx, hipMemsetAsync(ctx->d_status, 0, sizeof(Status), s));
     ARA_HIP(ctx, hipMemsetAsync(ctx->d_maxlen, 0, sizeof(unsigned long long), s));
+    // the occurrence count first: the event ids may be absent only when there
+    // are none (the validation reads ids only inside [0, offsets[n_trials]))
     int64_t n_occ = 0;
     ARA_HIP(ctx, hipMemcpyAsync(&n_occ, d_trial_offsets + n_trials, sizeof n_occ,
                                 hipMemcpyDeviceToHost, s));
+    ARA_HIP(ctx, hipStreamSynchronize(s));
+    if (n_occ > 0 && !d_event_ids)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_load_yet: no event ids for %lld occurrences",
+                    (long long)n_occ);
     if (n_trials > 0)
         ARA_HIP(ctx, launch_validate_yet(d_trial_offsets, d_event_ids, d_times, n_trials,
                                          n_catalogue, ctx->d_status, ctx->d_maxlen, s));

@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.tiny import GOLDEN, A, B, golden_worked_cases, random_tiny_case, worked_example
+from tests.tiny import (GOLDEN, A, B, golden_worked_cases, random_tiny_case, worked_example,
+                        yet_from_lists)
 from workloads import config_small, make_yet
 
 torch = pytest.importorskip("torch")
@@ -104,6 +105,28 @@ def test_worked_example_exact(ara):
     r2 = ara.run(y, p2, diagnostics=True)
     assert r2["ylt"].cpu().numpy()[0].tolist() == [6.0e5, 0.0, 0.0, 3.4e6]
     assert r2["hits"].cpu().numpy()[0].tolist() == [5, 1, 0, 6]
+
+
+def test_empty_inputs(ara):
+    """A YET whose trials are all empty (no occurrence, so no event-id array
+    is needed on the device) through both kernels, with the occurrence view
+    and the hit counts, and a run over no trial: every YLT entry is 0."""
+    yet = yet_from_lists([[], [], [], []], 4)
+    _, pf = worked_example()
+    say("empty inputs")
+    y = ara.load_yet(yet)
+    for su in (False, True):
+        pf.su_enabled = su
+        p = ara.load_portfolio(pf, yet.n_catalogue)
+        r = ara.run(y, p, diagnostics=su, occ_view=True)
+        assert r["ylt"].cpu().numpy().tolist() == [[0.0] * 4], su
+        assert r["ylt_pf"].cpu().numpy().tolist() == [0.0] * 4, su
+        if su:
+            assert r["hits"].cpu().numpy().tolist() == [[0] * 4]
+        r0 = ara.run(y, p, trial_begin=2, trial_count=0)
+        assert tuple(r0["ylt"].shape) == (1, 0) and r0["ylt_pf"].numel() == 0
+        ara.free_portfolio(p)
+    ara.free_yet(y)
 
 
 @pytest.mark.parametrize("corr", [False, True])
