@@ -107,6 +107,38 @@ def test_worked_example_exact(ara):
     assert r2["hits"].cpu().numpy()[0].tolist() == [5, 1, 0, 6]
 
 
+@pytest.mark.parametrize("su", [False, True])
+def test_ragged_long_trials(ara, su):
+    """Trial lengths around every boundary of the kernels (one wavefront of
+    64 occurrences, a 512-occurrence segment, a 1,280-id pass) and one trial
+    of 50,000 occurrences (about a hundred segments): YLT, hit counts and the
+    occurrence view against the oracle."""
+    from workloads import INF
+    rng = np.random.default_rng(21)
+    lengths = [50_000, 0, 1, 63, 64, 65, 511, 512, 513, 1025, 1279, 1280, 1281, 3000, 0, 7]
+    w = config_small(su=su, n_trials=1)
+    trials = [list(rng.integers(0, w.yet.n_catalogue, size=n)) for n in lengths]
+    yet = yet_from_lists(trials, w.yet.n_catalogue)
+    pf = w.portfolio
+    pf.layers[0].agg_limit = INF                     # keep the long trial's loss informative
+    say("ragged long trials, su", su)
+    ref = oracle.run_ara(yet, pf, occ_view=True)
+    y = ara.load_yet(yet)
+    p = ara.load_portfolio(pf, yet.n_catalogue)
+    r = ara.run(y, p, diagnostics=su, occ_view=True)
+    check_t2(r["ylt"], ref, "ragged")
+    if su:
+        assert np.array_equal(r["hits"].cpu().numpy(), ref["hits"])
+        assert np.array_equal(r["hit_chk"].cpu().numpy().view(np.uint64), ref["hit_chk"])
+    d = r["occ_view"].double().cpu().numpy()
+    G = np.repeat(ref["gross"], np.diff(yet.offsets), axis=1)
+    assert np.all(np.abs(d - ref["occ_view"]) <= 2 * (1e-5 * G + 1e-3))
+    lean = ara.run(y, p, occ_view=True)              # the lean pass: the same view
+    assert torch.equal(lean["occ_view"], r["occ_view"])
+    ara.free_portfolio(p)
+    ara.free_yet(y)
+
+
 def test_empty_inputs(ara):
     """A YET whose trials are all empty (no occurrence, so no event-id array
     is needed on the device) through both kernels, with the occurrence view
