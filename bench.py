@@ -60,9 +60,9 @@ VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "588"))
 # 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
 # the counters were taken with; null otherwise.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "df1a58214dcef546b09d85b04bbef076f1424330e724b560a6bca46d43d45534",
-    "su_main_bytes": 27.244e9 + 0.1070e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0884e9 + 0.0306e9,        # k_ara_pu: fetch + write, 1M trials
+    "sources_sha256": "2737bb2ac928657bce61d54ec3907df520cde3cdb91bdfd276b006351aa385e4",
+    "su_main_bytes": 27.252e9 + 0.1070e9,   # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0908e9 + 0.0089e9,        # k_ara_pu: fetch + write, 1M trials
 }
 
 
