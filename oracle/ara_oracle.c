@@ -32,8 +32,9 @@
  *       inside the trial, i the absolute trial index.
  *       sigma_C = 0 -> z = u_I exactly; sigma_I = 0 -> z = u_C exactly.
  *   R5  sigma = sigma_I + sigma_C feeds the Beta (raw sum, as written).
- *   R6  "a value very close to sigma_beta_max": if sigma_beta >= sigma_beta_max
- *       use (1 - 1e-6) * sigma_beta_max.
+ *   R6  Section 3.3 caps the standard deviation fed to the Beta fit just below
+ *       sigma_beta_max without giving the margin: if sigma_beta >=
+ *       sigma_beta_max use (1 - 1e-6) * sigma_beta_max.
  *   R7  sigma = 0 or secondary uncertainty off -> loss = mean, no draw.
  *   R8  PML(RP) = k-th largest trial loss, TVaR(RP) = mean of the k largest,
  *       with k = max(1, floor(N / RP)).
@@ -399,24 +400,28 @@ int orc_ara_run(int64_t n_trials, int64_t trial_base, const int64_t *offsets,
 #else
     (void)n_threads;
 #endif
-    for (int32_t l = 0; l < n_layers; ++l) {                     /* layer loop */
+    /* Every layer is priced on every trial independently (section 2.2); a
+     * trial's occurrences are visited in stored (ascending time) order and,
+     * for each, every ELT of the layer in its listed order. */
+    for (int32_t l = 0; l < n_layers; ++l) {
         double occR = layer_terms[4 * l + 0], occL = layer_terms[4 * l + 1];
         double aggR = layer_terms[4 * l + 2], aggL = layer_terms[4 * l + 3];
 #pragma omp parallel for schedule(static)
-        for (int64_t t = 0; t < n_trials; ++t) {                 /* trial loop */
+        for (int64_t t = 0; t < n_trials; ++t) {
             uint32_t i_abs = (uint32_t)(trial_base + t);
             double S = 0.0, A_prev = 0.0, G = 0.0;
             int64_t nh = 0;
             uint64_t chk = 0;
             int64_t base = offsets[t];
-            for (int64_t j = base; j < offsets[t + 1]; ++j) {     /* event loop */
+            for (int64_t j = base; j < offsets[t + 1]; ++j) {
                 uint32_t k = (uint32_t)(j - base);
                 int32_t E = event_ids[j];
                 double X = 0.0;
-                for (int32_t e = 0; e < n_elt; ++e) {             /* ELT loop */
+                for (int32_t e = 0; e < n_elt; ++e) {
                     if (elt_layer[e] != l) continue;
-                    int64_t r = dat[(int64_t)e * n_catalogue + E];   /* lookup */
-                    if (r < 0) continue;                             /* zero loss */
+                    /* direct-access table: -1 marks an event the ELT does not cover */
+                    int64_t r = dat[(int64_t)e * n_catalogue + E];
+                    if (r < 0) continue;
                     ++nh;
                     chk += (uint64_t)(k + 1) * 2654435761ull + (uint64_t)elt_id[e];
                     double mu = row_mean[r];
@@ -428,12 +433,12 @@ int orc_ara_run(int64_t n_trials, int64_t trial_base, const int64_t *offsets,
                                                   (uint32_t)E, keying, seed);
                     double lp = elt_terms[3 * e + 2] *
                                 clamp_terms(loss, elt_terms[3 * e + 0], elt_terms[3 * e + 1]);
-                    X += lp;                                          /* accumulate */
+                    X += lp;                       /* event loss X_k over the layer's ELTs */
                 }
                 G += X;
-                double O = clamp_terms(X, occR, occL);               /* occurrence */
-                S += O;
-                double A = clamp_terms(S, aggR, aggL);               /* aggregate */
+                double O = clamp_terms(X, occR, occL);     /* occurrence terms on X_k */
+                S += O;                                    /* running sum, never clamped */
+                double A = clamp_terms(S, aggR, aggL);     /* aggregate terms on S_k (R2) */
                 if (occ_view) occ_view[(int64_t)l * occ_total + (j - offsets[0])] = A - A_prev;
                 A_prev = A;
             }

@@ -687,3 +687,118 @@ def test_oracle_matches_its_stored_small_results():
         np.testing.assert_allclose(tvar, case["tvar"], rtol=1e-12)
         np.testing.assert_allclose(r["ylt_pf"][:16], case["ylt_head"], rtol=1e-12)
         assert math.isclose(float(r["ylt_pf"].sum()), case["ylt_sum"], rel_tol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# The sigma cap of section 3.3 and the near-Bernoulli shapes it produces
+# --------------------------------------------------------------------------
+# When sigma_b >= sigma_b,max = sqrt(mu_b (1 - mu_b)) the fit uses
+# (1 - eps) sigma_b,max instead (eps = 1e-6, the reading of "a value very close
+# to sigma_b,max").  Then (sigma_b,max / sigma_b)^2 - 1 = (1 - eps)^-2 - 1 for
+# every capped row, so the fit is alpha = mu_b k, beta = (1 - mu_b) k with the
+# single constant k below, whatever the row's mean, sigma or exposure; and a
+# Beta(alpha, beta) has variance mu_b (1 - mu_b) / (alpha + beta + 1), which
+# must equal the capped sigma_b squared.  Neither fact retypes the oracle's
+# branch: the first is the cap's algebra done once in 50 digits, the second
+# is the Beta distribution's variance.
+def _kappa_eps():
+    mp.mp.dps = 50
+    return (1 - mp.mpf("1e-6")) ** -2 - 1
+
+
+@pytest.mark.parametrize("mu,sigma,mx", [
+    (2.0, 2.0, 4.0),          # sigma_b = sigma_b,max exactly (mu_b = 1/2): the cap applies
+    (1.0, 3.0, 4.0),          # the sigma-capped test rows: sigma_I = 3 mean, max = 4 mean
+    (0.1, 0.9, 1.0), (9.0, 5.0, 10.0), (1e6, 2.5e6, 3e6), (0.25, 2.0, 0.5)])
+def test_sigma_cap_fit_closed_form(mu, sigma, mx):
+    a, b = O.beta_fit(mu, sigma, mx)
+    k = _kappa_eps()
+    mu_b = mp.mpf(mu) / mp.mpf(mx)
+    # FP64 forms k as the difference of (sigma_b,max / sigma_b)^2 ~ 1 + 2e-6 and
+    # 1, which leaves about 1e-16 / 2e-6 = 5e-11 of relative precision; a slip
+    # (the cap on sigma_b^2, '>' for '>=', another eps) moves k by O(1)
+    tol = 1e-9
+    assert abs(mp.mpf(a) - mu_b * k) <= tol * mu_b * k, (a, mu_b * k)
+    assert abs(mp.mpf(b) - (1 - mu_b) * k) <= tol * (1 - mu_b) * k, (b, (1 - mu_b) * k)
+    # the fitted Beta's standard deviation is the capped sigma_b
+    var = mu_b * (1 - mu_b) / (mp.mpf(a) + mp.mpf(b) + 1)
+    s_max = mp.sqrt(mu_b * (1 - mu_b))
+    assert abs(mp.sqrt(var) / ((1 - mp.mpf("1e-6")) * s_max) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("mu,mx,below", [(2.0, 4.0, 1e-3), (1.0, 4.0, 1e-9), (0.3, 1.0, 0.25),
+                                         (7.0, 8.0, 1e-5)])
+def test_sigma_below_cap_keeps_moments(mu, mx, below):
+    """Just below sigma_b,max no cap applies: the fit reproduces the row's
+    mean and standard deviation (Beta mean alpha/(alpha+beta), variance
+    mu_b (1-mu_b)/(alpha+beta+1))."""
+    mp.mp.dps = 50
+    mu_b = mp.mpf(mu) / mp.mpf(mx)
+    s_max = mp.sqrt(mu_b * (1 - mu_b))
+    sigma = float(s_max * (1 - mp.mpf(below)) * mp.mpf(mx))
+    a, b = O.beta_fit(mu, sigma, mx)
+    A_, B_ = mp.mpf(a), mp.mpf(b)
+    assert abs(A_ / (A_ + B_) - mu_b) < 1e-12 * mu_b
+    s_b = mp.mpf(sigma) / mp.mpf(mx)
+    sd = mp.sqrt(mu_b * (1 - mu_b) / (A_ + B_ + 1))
+    # the moment fit loses ~ eps / (1 - s_b/s_max) of relative precision
+    assert abs(sd / s_b - 1) < 1e-15 / float(below) + 1e-13, (sd / s_b - 1)
+
+
+def _near_bernoulli_shapes():
+    k = float(_kappa_eps())
+    out = [(mu_b * k, (1 - mu_b) * k) for mu_b in (0.25, 0.5, 0.1, 0.9)]
+    return out + [(1e-3, 1e-3), (5e-4, 2e-3), (1e-3, 1e-2), (3e-3, 1e-4)]
+
+
+def _grid_points(a, b):
+    """Draw-grid values of z (odd multiples of 2^-24): spread over (0, 1),
+    plus the narrow bands next to the mass split I_(1/2)(a, b) where the
+    roots are representable doubles."""
+    mp.mp.dps = 50
+    ih = mp.betainc(a, b, 0, mp.mpf("0.5"), regularized=True)
+    j = [1, 3, 101, 2 ** 20 + 1, 2 ** 22 + 1, 2 ** 23 - 1, 2 ** 23 + 1, 3 * 2 ** 22 + 1,
+         2 ** 24 - 101, 2 ** 24 - 3, 2 ** 24 - 1]
+    c = int(ih * 2 ** 24) | 1
+    for d in (-40001, -4001, -401, -41, -5, -1, 1, 5, 41, 401, 4001, 40001):
+        jj = c + 2 * d
+        if 0 < jj < 2 ** 24:
+            j.append(jj)
+    return sorted(set(j))
+
+
+@pytest.mark.parametrize("a,b", _near_bernoulli_shapes())
+def test_betaincinv_near_bernoulli_brackets(a, b):
+    """The oracle's Beta inverse at the near-Bernoulli shapes the cap makes
+    (alpha, beta ~ 1e-6) and at alpha, beta ~ 1e-3, on the draw grid, against
+    mpmath's 50-digit regularized incomplete beta, on the side where the root
+    is at most 1/2 (the other side through I_(1-x)(b, a) = 1 - z).  Near 0,
+    I_x ~ x^a / (a B(a, b)), so a relative change d of the root changes I by
+    a d: the root itself is conditioned like 1/a (2e6 here) and FP64 cannot
+    hold it to 1e-12.  What FP64 can hold is the backward error: I at the
+    returned root must equal z to 1e-13 relative (the forward error is then
+    at most 1e-13 / a).  Where the oracle returns an exact 0 the true root
+    must lie below 1e-300 (I at 1e-300 already exceeds z)."""
+    mp.mp.dps = 50
+    js = np.array(_grid_points(a, b), np.float64)
+    z = js / 2 ** 24
+    zc = (2 ** 24 - js) / 2 ** 24
+    x, xc = O.betaincinv(np.full(z.size, a), np.full(z.size, b), z, zc, complement=True)
+    A_, B_ = mp.mpf(a), mp.mpf(b)
+    n_inner = 0
+    for zi, zci, xi, xci, ji in zip(z, zc, x, xc, js):
+        Z, ZC = mp.mpf(int(ji)) / 2 ** 24, mp.mpf(2 ** 24 - int(ji)) / 2 ** 24
+        if xi <= 0.5:
+            s, t, S, T = A_, B_, Z, mp.mpf(xi)
+        else:
+            s, t, S, T = B_, A_, ZC, mp.mpf(xci)
+        if T == 0:
+            # below the smallest double: the root must be under 1e-300
+            assert mp.betainc(s, t, 0, mp.mpf("1e-300"), regularized=True) >= S, (a, b, ji)
+        else:
+            back = abs(mp.betainc(s, t, 0, T, regularized=True) / S - 1)
+            assert back < 1e-13, (a, b, ji, float(T), float(back))
+            n_inner += 1
+        assert abs(xi + xci - 1.0) <= 2.3e-16
+    # the bands next to the mass split give roots inside the double range
+    assert n_inner >= 4
