@@ -25,6 +25,16 @@ Two further modes print their own JSON line:
                   layers, 2-32 ELTs per layer, trial ranges of 1e4-1e6 trials):
                   p50 / p99 latency and throughput at several offered loads,
                   against a one-at-a-time server with the measured service times.
+  --mode probes   the measurement probes behind the roofline figures: the VALU
+                  issue rate of single instruction kinds, the streaming read
+                  bandwidth, and the per-draw arithmetic alone (Philox and the
+                  FP32 Beta quantile at the full-shape row shape).
+  --mode variants the full-shape YET with the secondary-uncertainty laws that
+                  use the FP64-capable second pass: sigma_I = sigma_C = mean/4
+                  (section 3.2's two-normal mix), rows of varied Beta shapes
+                  (sigma_I / mean 0.15-0.9, max / mean 1.5-10) and 30 % of rows
+                  above the sigma cap (section 3.3); time per run and evaluations/s
+                  beside the headline law.
   --mode views    the outputs either side of the YLT on the full shape: ara_run
                   with the per-occurrence view (secondary uncertainty on and
                   off; 1e9 FP32 increments written) and ara_ep_curve on the
@@ -42,27 +52,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# VALU issue peak in 32-bit lane operations: the FP32 vector peak of
-# 157.3 TFLOP/s counts an FMA as two flops, i.e. 256 CUs x 128 lanes x 2.4 GHz
-# = 78.6e12 lane operations per second.
-PEAK_VALU_TOPS = 157.3 / 2.0
-# VALU lane operations per performed draw of the main SU kernel at the
-# full-shape workload: SQ_INSTS_VALU x 64 / performed draws, from rocprofv3
-# (profiles/ara_su_full_counters.md).  A draw is performed for a non-zero
-# lookup whose row can pay (its largest possible loss exceeds the ELT
-# retention, limit and share non-zero); the other non-zero lookups add
-# exactly 0 and are skipped.
-VALU_OPS_PER_DRAW = float(os.environ.get("ARA_VALU_OPS_PER_DRAW", "588"))
+# VALU lane-operation peak of the non-packed instructions the kernels are
+# built with: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane
+# operations per second (an FMA is one operation).  The FP32 vector figure of
+# 157.3 TFLOP/s counts an FMA as two flops and a packed instruction as two
+# lanes: 157.3 / 4 = 39.3.  Dependent chains of v_fma_f32, v_mul_f32,
+# v_mul_hi_u32, v_mad_u64_u32 or v_xor/v_add reach 0.96 of it at the clock the
+# part holds under load (bench.py --mode probes).
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# HBM-side traffic of one launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# of this workload (profiles/ara_su_full_counters.md), each scaled by what the
-# counter reads for an elementwise kernel that reads and writes 1 GiB (FETCH
-# 2.0, WRITE 1.0).  Reported only while the kernel sources hash to the value
-# the counters were taken with; null otherwise.
-PROFILED_TRAFFIC = {
-    "sources_sha256": "2737bb2ac928657bce61d54ec3907df520cde3cdb91bdfd276b006351aa385e4",
-    "su_main_bytes": 27.252e9 + 0.1070e9,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0908e9 + 0.0089e9,        # k_ara_pu: fetch + write, 1M trials
+# Counter figures of the current kernel sources (rocprofv3, one MI355X),
+# reported only while the sources hash to the value they were taken with and
+# null otherwise.
+#  * draw_arith_ops: arithmetic lane operations per draw of the method's own
+#    per-draw work -- Philox4x32-10 and the FP32 Beta quantile at the
+#    full-shape row shape, run alone by k_probe_draws with the shape table --
+#    counted as SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 + _INT32 + _INT64 per
+#    wavefront of 64 draws (moves, selects, compares and lane operations are
+#    not the method's arithmetic and are left out).
+#  * su_main_bytes / pu_bytes: HBM-side traffic of one launch at 1,000,000
+#    trials, FETCH_SIZE and WRITE_SIZE each scaled by what the counter reads
+#    for an elementwise kernel that reads and writes 1 GiB (FETCH 2.0,
+#    WRITE 1.0).
+PROFILED = {
+    "sources_sha256": None,
+    "draw_arith_ops": None,
+    "su_main_bytes": None,
+    "pu_bytes": None,
 }
 
 
@@ -73,7 +89,8 @@ def kernel_sources_sha256():
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1501_06326_amd", "csrc")
-    for f in ("ara_kernels.hip", "ara_math.h", "ara_internal.h", "ara_kernels.h"):
+    for f in ("ara_kernels.hip", "ara_math.h", "ara_internal.h", "ara_kernels.h",
+              "ara_probe.hip"):
         with open(os.path.join(csrc, f), encoding="utf-8") as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
@@ -83,9 +100,9 @@ def kernel_sources_sha256():
 
 
 def profiled(key):
-    if kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+    if kernel_sources_sha256() != PROFILED["sources_sha256"]:
         return None
-    return PROFILED_TRAFFIC[key]
+    return PROFILED[key]
 
 
 def live_draws(yet, pf):
@@ -118,12 +135,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sum-mode", default="naive32")
+    ap.add_argument("--sum-mode", default="kahan32")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one elementwise kernel that reads and writes 1 GiB (a "
                          "known-size kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--mode", choices=["step", "batched", "served", "precision", "views"],
-                    default="step")
+    ap.add_argument("--mode", choices=["step", "batched", "served", "precision", "views",
+                                       "probes", "variants"], default="step")
     ap.add_argument("--oracle-trials", type=int, default=3000, help="precision mode")
     ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
     ap.add_argument("--graph", action="store_true", help="batched mode: also time a graph replay")
@@ -145,6 +162,10 @@ def main():
         return bench_precision(args)
     if args.mode == "views":
         return bench_views(args)
+    if args.mode == "probes":
+        return bench_probes(args)
+    if args.mode == "variants":
+        return bench_variants(args)
 
     import torch
     from paper_1501_06326_amd import Ara, evaluations
@@ -231,24 +252,65 @@ def main():
         "pml": [float(v) for v in pml],
         "tvar": [float(v) for v in tvar],
     }
-    ops = VALU_OPS_PER_DRAW * draws
+    # live ceilings of the same part in the same run: the streaming read of the
+    # event-id array (4 GB, 16-byte non-temporal loads) and the per-draw
+    # arithmetic alone at the full-shape row shape (k_probe_draws)
+    from paper_1501_06326_amd import ara as A
+    sh = stream.cuda_stream
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = (4 * yet.n_occ) // 16 * 16
+    ev_s = torch.cuda.Event(enable_timing=True)
+    ev_e = torch.cuda.Event(enable_timing=True)
+    A.ara_probe_stream_read(ara.ctx, ev.data_ptr(), nbytes, sink.data_ptr(), sh)
+    ev_s.record(stream)
+    for _ in range(5):
+        A.ara_probe_stream_read(ara.ctx, ev.data_ptr(), nbytes, sink.data_ptr(), sh)
+    ev_e.record(stream)
+    torch.cuda.synchronize()
+    b9_gbs = nbytes / (ev_s.elapsed_time(ev_e) / 5 / 1e3) / 1e9
+    nd = 1 << 27
+    xd = torch.empty(nd, dtype=torch.float32, device=dev)
+    A.ara_probe_draws(ara.ctx, nd, pf.seed, 3, 2.75, 8.25, True, xd.data_ptr(), sh)
+    t0d = time.perf_counter()
+    A.ara_probe_draws(ara.ctx, nd, pf.seed, 3, 2.75, 8.25, True, xd.data_ptr(), sh)
+    draw_ceiling = nd / (time.perf_counter() - t0d)       # synchronous call: wall time
+    del xd
+    log(f"ceilings: stream read {b9_gbs:.0f} GB/s, draw arithmetic alone {draw_ceiling:.3e} draws/s")
+
+    # algorithmic HBM bytes of one SU run: event ids + trial offsets + the
+    # layer's tables read once (pairs and compact records) + the two YLT outputs
+    su_bytes = 4 * yet.n_occ + 8 * (n + 1) + 8 * yet.n_catalogue + 32 * 20000 * 16 + 2 * 4 * n
+    arith = profiled("draw_arith_ops")
+    ops = arith * draws if arith else None
     result["roofline"] = {
         "kernel": "k_ara_su (+ k_ara_su_redo), ara_run",
         "bound": "alu",
         "achieved": (ops / (run_ms / 1e3) / 1e12) if ops else None,
         "peak": PEAK_VALU_TOPS,
-        "unit": "TOP/s",
+        "unit": "T lane-ops/s",
         "frac": (ops / (run_ms / 1e3) / 1e12 / PEAK_VALU_TOPS) if ops else None,
         "traffic": profiled("su_main_bytes") if (args.trials == 1_000_000 and
                                                   args.catalogue == 100_000) else None,
         "launch_ms": run_ms,
         "draws_per_s": draws / (run_ms / 1e3),
-        "valu_ops_per_draw": VALU_OPS_PER_DRAW or None,
+        "draw_arith_ops": arith,
+        "draw_arithmetic_ceiling_draws_per_s": draw_ceiling,
+        "frac_of_draw_arithmetic_ceiling": draws / (run_ms / 1e3) / draw_ceiling,
+        "hbm": {"bytes": su_bytes, "achieved_gbs": su_bytes / (run_ms / 1e3) / 1e9,
+                "frac_of_peak": su_bytes / (run_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+                "stream_read_gbs": b9_gbs,
+                "frac_of_stream_read": su_bytes / (run_ms / 1e3) / 1e9 / b9_gbs},
     }
 
     if not args.no_pu:
         pf_pu = full_portfolio(su=False, n_catalogue=args.catalogue)
+        # the per-event occurrence-loss table is built at load: row upload,
+        # Beta-fit kernel, per-event fill and sparse form (synchronous call)
+        ara.load_portfolio(pf_pu, yet.n_catalogue)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
         p_pu = ara.load_portfolio(pf_pu, yet.n_catalogue)
+        build_ms = 1e3 * (time.perf_counter() - tb)
         for _ in range(3):
             ara.run(y, p_pu, out_layers=out_l, out_pf=out_p, sync=False)
         torch.cuda.synchronize()
@@ -267,12 +329,14 @@ def main():
         gbs = byts / (pu_ms / 1e3) / 1e9
         result["pu_path"] = {
             "ms_per_run": pu_ms, "evaluations_per_s": evals / (pu_ms / 1e3),
+            "table_build_ms": build_ms,
+            "evaluations_per_s_with_table_build": evals / ((pu_ms + build_ms) / 1e3),
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": gbs / PEAK_HBM_GBS,
+                         "frac": gbs / PEAK_HBM_GBS, "frac_of_stream_read": gbs / b9_gbs,
                          "traffic": profiled("pu_bytes") if args.catalogue == 100_000 else None,
                          "bytes": byts},
         }
-        log(f"PU: {pu_ms:.3f} ms/run, {gbs:.0f} GB/s")
+        log(f"PU: {pu_ms:.3f} ms/run, {gbs:.0f} GB/s; table build {build_ms:.2f} ms")
 
     if not args.no_cpu_baseline:
         import oracle
@@ -312,6 +376,129 @@ def _full_yet(n_trials):
     yet = make_yet(n_trials, 1000.0, 100_000, SEED_YET_FULL, with_times=False)
     log(f"generated YET: {n_trials} trials, {yet.n_occ} occurrences in {time.time() - t0:.1f}s")
     return yet
+
+
+def bench_probes(args):
+    """VALU issue rates per instruction kind, the streaming read bandwidth and
+    the per-draw arithmetic alone (one JSON line)."""
+    import torch
+    from paper_1501_06326_amd import Ara
+    from paper_1501_06326_amd import ara as A
+
+    ara = Ara(0)
+    dev = ara.device
+    props = torch.cuda.get_device_properties(dev)
+    n_cu = props.multi_processor_count
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res = {"metric": "probes", "n_cu": n_cu, "valu": {}}
+    wps, iters = 8, 8192
+    out = torch.empty(A.ara_probe_valu_lanes(ara.ctx, wps), dtype=torch.float32, device=dev)
+    for name, kind in A.PROBE_KINDS.items():
+        instr = [0]
+
+        def run():
+            instr[0] = A.ara_probe_valu(ara.ctx, kind, wps, iters, out.data_ptr(), sh)
+        ms = timed(run, 5)
+        rate = instr[0] / (ms / 1e3)
+        # wave instructions per SIMD per cycle at the 2.4 GHz peak engine clock
+        per_simd_clk = rate / (n_cu * 4 * 2.4e9)
+        res["valu"][name] = {"ms": ms, "wave_instr": instr[0], "wave_instr_per_s": rate,
+                             "lane_ops_per_s": 64 * rate, "per_simd_per_clk_at_2.4GHz": per_simd_clk}
+        log(f"valu {name}: {ms:.3f} ms, {64 * rate / 1e12:.1f} T lane-ops/s, "
+            f"{per_simd_clk:.3f} wave-instr per SIMD-clock")
+    # streaming read of 4 GiB (the size of the full-shape event-id stream)
+    nbytes = 4 << 30
+    buf = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    ms = timed(lambda: A.ara_probe_stream_read(ara.ctx, buf.data_ptr(), nbytes, sink.data_ptr(),
+                                               sh), 10)
+    res["stream_read"] = {"bytes": nbytes, "ms": ms, "gbs": nbytes / (ms / 1e3) / 1e9}
+    log(f"stream read: {ms:.3f} ms for 4 GiB, {nbytes / (ms / 1e3) / 1e9:.0f} GB/s")
+    del buf
+    # the per-draw arithmetic alone at the full-shape row shape (mean/max 1/4,
+    # sigma/max 1/8: alpha = 2.75, beta = 8.25)
+    nd = 1 << 28
+    x = torch.empty(nd, dtype=torch.float32, device=dev)
+    for tab in (True, False):
+        ms = timed(lambda: A.ara_probe_draws(ara.ctx, nd, 150106326, 3, 2.75, 8.25, tab,
+                                             x.data_ptr(), sh), 5)
+        bad = int((x < 0).sum().item())
+        key = "draws" if tab else "draws_closed_form_guess"
+        res[key] = {"n": nd, "shape": [2.75, 8.25], "shape_table": tab, "ms": ms,
+                    "draws_per_s": nd / (ms / 1e3), "not_converged": bad}
+        log(f"draws alone ({'shape table' if tab else 'closed-form guess'}): {ms:.3f} ms for "
+            f"{nd}, {nd / (ms / 1e3):.3e} draws/s, {bad} not converged")
+    print(json.dumps(res), flush=True)
+    ara.close()
+
+
+def bench_variants(args):
+    """Full-shape runs under the laws that use the FP64-capable second pass."""
+    import copy
+    import torch
+    from paper_1501_06326_amd import Ara, evaluations
+    from workloads import (SEED_ELT_BASE, Layer, Portfolio, SEED_PHILOX, config_full, make_elt,
+                           sigma_capped, varied_shapes)
+
+    w = config_full(n_trials=args.trials, with_times=False)
+    yet, base = w.yet, w.portfolio
+    lay = base.layers[0]
+    corr = Portfolio(layers=[Layer(elts=[make_elt(e, 20_000, yet.n_catalogue, SEED_ELT_BASE + e,
+                                                  corr=True, retention=1e6, limit=5e7)
+                                         for e in range(16)],
+                                   occ_retention=lay.occ_retention, occ_limit=lay.occ_limit,
+                                   agg_retention=lay.agg_retention, agg_limit=lay.agg_limit)],
+                     seed=SEED_PHILOX, su_enabled=True)
+    cases = [("headline", base), ("two_normal_mix", corr), ("varied_shapes", varied_shapes(base)),
+             ("sigma_capped_30pct", sigma_capped(base))]
+    ara = Ara(0)
+    dev = ara.device
+    off = torch.from_numpy(yet.offsets).to(dev)
+    ev = torch.from_numpy(yet.event_ids).to(dev)
+    y = ara.load_yet(yet, device_arrays=(off, ev, None))
+    stream = torch.cuda.current_stream()
+    n = yet.n_trials
+    out_p = torch.empty(n, dtype=torch.float32, device=dev)
+    scratch = torch.empty(ara.run_scratch_size(n), dtype=torch.uint8, device=dev)
+    res = {}
+    for name, pf in cases:
+        p = ara.load_portfolio(pf, yet.n_catalogue)
+        ara.run(y, p, out_pf=out_p, layers=False, scratch=scratch)      # warmup, status check
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ara.run(y, p, out_pf=out_p, layers=False, scratch=scratch, sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ara.sync_status()
+        ms = e0.elapsed_time(e1) / args.steps
+        ev_n = evaluations(yet, pf)
+        res[name] = {"ms_per_run": ms, "evaluations_per_s": ev_n / (ms / 1e3)}
+        log(f"{name}: {ms:.2f} ms per run, {ev_n / (ms / 1e3):.3e} evaluations/s")
+        ara.free_portfolio(p)
+        del p
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "trial*event*ELT evaluations/s per secondary-uncertainty law",
+                      "n_gpus": 1, "steps": args.steps, "dtype": "f32 (FP64 second pass)",
+                      "data": "synthetic (seeded numpy generator; lognormal ELT means)",
+                      "config": {"workload": w.name, "trials": n, "occurrences": yet.n_occ,
+                                 "elts": 16, "sum_mode": "kahan32"}, **res}), flush=True)
+    ara.close()
 
 
 def bench_batched(args):

@@ -74,7 +74,9 @@ enum {
     ARA_E_UNSUPPORTED = -10          /* option combination not supported */
 };
 
-enum { ARA_SUM_NAIVE32 = 0, ARA_SUM_KAHAN32 = 1, ARA_SUM_F64 = 2 };
+/* How a trial's occurrence losses are summed: compensated FP32 (Neumaier;
+ * the default, value 0), plain FP32, or FP64. */
+enum { ARA_SUM_KAHAN32 = 0, ARA_SUM_NAIVE32 = 1, ARA_SUM_F64 = 2 };
 enum { ARA_F32 = 0, ARA_F64 = 1 };
 
 typedef struct ara_context ara_context;
@@ -130,12 +132,15 @@ typedef struct {
     int32_t sum_mode;           /* ARA_SUM_*: how a trial's occurrence losses are summed */
     int32_t ylt_dtype;          /* ARA_F32 or ARA_F64 for both YLT outputs */
     float tail_band;            /* z or 1-z below this use the FP64 quantile; <= 0: 2^-24 */
-    int32_t reserved;
+    int32_t debug_flags;        /* 0, or ARA_DEBUG_* (tests of the failure paths) */
     int64_t *d_hits;            /* optional [n_layers][trial_count]: non-zero lookups */
     uint64_t *d_hit_chk;        /* optional [n_layers][trial_count]: sum over hits of
                                    (k+1)*2654435761 + elt_id, modulo 2^64 */
-    void *d_scratch;            /* optional: ara_run_scratch_size() bytes of device scratch;
-                                   NULL = a buffer the context keeps (grown on demand) */
+    void *d_scratch;            /* ara_run_scratch_size(trial_count) bytes of device scratch
+                                   (the trials handed from the FP32 pass to the FP64-capable
+                                   pass); required for portfolios with secondary
+                                   uncertainty, unused without.  Runs that overlap in time
+                                   need scratch of their own. */
     size_t scratch_bytes;
     void *d_occ_view;           /* optional occurrence view (section 2.2, aggregate terms):
                                    element l * occ_view_stride + (j - offsets[trial_begin])
@@ -149,6 +154,13 @@ typedef struct {
                                    occurrences; a larger index is not written and the run
                                    reports ARA_E_WORKSPACE_TOO_SMALL through ara_sync_status) */
 } ara_run_opts;
+
+/* ara_run_opts.debug_flags.  ARA_DEBUG_QUANTILE_ONE_STEP sends every draw to
+ * the FP64 quantile and lets that iteration take a single step, so draws
+ * whose start is not already a root are reported as non-converging
+ * (ARA_E_NUMERIC through ara_sync_status) while every kernel ends normally;
+ * for tests of the convergence check (section 5.1's criterion) only. */
+#define ARA_DEBUG_QUANTILE_ONE_STEP 1
 
 /* ---- context ------------------------------------------------------------ */
 ara_status ara_create(int hip_device, ara_context **out);
@@ -188,9 +200,11 @@ ara_status ara_free_portfolio(ara_context *ctx, ara_portfolio *pf);
  * Runs trials [trial_begin, trial_begin + trial_count) and writes
  * d_ylt_layers[l * trial_count + t] (loss of layer l in trial trial_begin+t)
  * and d_ylt_portfolio[t] (sum over layers), in opts->ylt_dtype; either output
- * may be NULL.  opts may be NULL (all trials, NAIVE32, F32).  Asynchronous:
- * returns after enqueueing on the stream; a quantile failure is reported by
- * ara_sync_status. */
+ * may be NULL.  opts may be NULL (all trials, KAHAN32, F32) for portfolios
+ * without secondary uncertainty; with it, opts->d_scratch is required
+ * (ARA_E_WORKSPACE_TOO_SMALL otherwise).  The call allocates nothing.
+ * Asynchronous: returns after enqueueing on the stream; a quantile failure is
+ * reported by ara_sync_status. */
 ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
                    const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
                    void *stream);
@@ -198,6 +212,7 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
 /* Device scratch an ara_run over trial_count trials needs (the list of
  * trials handed from the FP32 pass to the FP64-capable pass). */
 ara_status ara_run_scratch_size(int64_t trial_count, size_t *bytes);
+
 
 /* Synchronises the stream and reports ARA_E_NUMERIC (with the first failing
  * trial, occurrence and elt_id in the message) if a run since the last call
@@ -287,7 +302,7 @@ typedef struct ara_server ara_server;
 typedef struct {
     int32_t max_inflight;       /* request groups in flight (streams); <= 0: 4 */
     int32_t max_batch;          /* requests per batched launch; <= 0: 16 */
-    int32_t sum_mode;           /* ARA_SUM_* */
+    int32_t sum_mode;           /* ARA_SUM_* (0: KAHAN32) */
     int32_t reserved;
     void *d_pool;               /* device memory the server sub-allocates requests from */
     size_t pool_bytes;
@@ -371,6 +386,53 @@ ara_status ara_debug_philox(ara_context *ctx, int64_t n, const uint32_t *d_ctr, 
 ara_status ara_debug_beta_quantile(ara_context *ctx, int64_t n, const float *d_a,
                                    const float *d_b, const double *d_z, const double *d_zc,
                                    float tail_band, float *d_x, int32_t *d_path, void *stream);
+/* ara_debug_beta_quantile_shape: the same for n draws of one shape (a, b in
+ * [1, 32]) through the path of rows whose shape has a table: the table is
+ * built as a portfolio load builds it (in device memory allocated for the
+ * call) and the FP32 quantile starts from it.  Synchronises the stream. */
+ara_status ara_debug_beta_quantile_shape(ara_context *ctx, int64_t n, float a, float b,
+                                         const double *d_z, const double *d_zc, float *d_x,
+                                         int32_t *d_path, void *stream);
+
+/* ---- measurement probes (the roofline figures of the benchmark) -----------
+ * ara_probe_stream_read: reads bytes (a multiple of 16) of device memory at
+ *   d_src (16-byte aligned) once with 16-byte non-temporal loads, the access
+ *   pattern of the event-id stream, and XORs a digest into *d_sink (one
+ *   device word); the duration gives the streaming bandwidth of the part.
+ *   Asynchronous.
+ * ara_probe_valu: eight independent chains of one vector instruction kind per
+ *   lane (ARA_PROBE_*), iters rounds, waves_per_simd wavefronts on each SIMD of
+ *   the device; d_out receives one float per lane (n_cu * 4 * waves_per_simd *
+ *   64 floats, ara_probe_valu_lanes) and *valu_instr (host) the wavefront
+ *   instructions of the chains (8 * iters per wavefront; 16 * iters for
+ *   ARA_PROBE_XAD_U32, an xor and an add, and ARA_PROBE_MAD_U64_U32, a
+ *   product and an xor).  Asynchronous.
+ * ara_probe_draws: the per-draw arithmetic of secondary uncertainty alone
+ *   (section 3): n draws of one ELT row of shape (a, b), Philox4x32-10 keyed
+ *   (j mod 1024, j / 1024, elt_id, 0) with key = seed, the draw on the 2^-24
+ *   grid and the FP32 Beta quantile (the analysis' bulk path), started from
+ *   the shape's table when use_shape_table is non-zero (the path of rows
+ *   whose shape has a table) or from the closed-form guess otherwise; d_x[j]
+ *   receives the quantile (-1 where the FP32 iteration did not converge).
+ *   a, b must lie in [1, 32].  Synchronises the stream (the quantile's
+ *   continued-fraction term counts and the table are made on the device
+ *   first, the table in 1.3 KB of device memory allocated for the call). */
+enum {
+    ARA_PROBE_FMA_F32 = 0,     /* v_fma_f32 */
+    ARA_PROBE_MUL_F32 = 1,     /* v_mul_f32 */
+    ARA_PROBE_XAD_U32 = 2,     /* (x ^ m) + c */
+    ARA_PROBE_MULHI_U32 = 3,   /* high word of a 32 x 32 product (Philox) */
+    ARA_PROBE_MAD_U64_U32 = 4, /* full 64-bit 32 x 32 product, halves xor-ed (Philox) */
+    ARA_PROBE_EXP2_F32 = 5,    /* transcendental 2^x */
+    ARA_PROBE_FMA_F64 = 6      /* v_fma_f64 */
+};
+ara_status ara_probe_stream_read(ara_context *ctx, const void *d_src, size_t bytes,
+                                 uint32_t *d_sink, void *stream);
+ara_status ara_probe_valu_lanes(ara_context *ctx, int32_t waves_per_simd, int64_t *lanes);
+ara_status ara_probe_valu(ara_context *ctx, int32_t kind, int32_t waves_per_simd, int32_t iters,
+                          float *d_out, uint64_t *valu_instr, void *stream);
+ara_status ara_probe_draws(ara_context *ctx, int64_t n, uint64_t seed, uint32_t elt_id, float a,
+                           float b, int32_t use_shape_table, float *d_x, void *stream);
 
 #ifdef __cplusplus
 }

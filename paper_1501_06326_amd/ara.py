@@ -30,7 +30,8 @@ ARA_E_WORKSPACE_TOO_SMALL = -8
 ARA_E_NUMERIC = -9
 ARA_E_UNSUPPORTED = -10
 
-ARA_SUM_NAIVE32, ARA_SUM_KAHAN32, ARA_SUM_F64 = 0, 1, 2
+ARA_SUM_KAHAN32, ARA_SUM_NAIVE32, ARA_SUM_F64 = 0, 1, 2
+ARA_DEBUG_QUANTILE_ONE_STEP = 1
 ARA_F32, ARA_F64 = 0, 1
 SUM_MODES = {"naive32": ARA_SUM_NAIVE32, "kahan32": ARA_SUM_KAHAN32, "f64": ARA_SUM_F64}
 
@@ -42,7 +43,12 @@ EXPORTS = ["ara_create", "ara_destroy", "ara_status_string", "ara_last_error", "
            "ara_batch_autotune", "ara_batch_graph_create", "ara_graph_launch",
            "ara_graph_destroy", "ara_server_create", "ara_server_submit", "ara_server_poll",
            "ara_server_release", "ara_server_destroy", "ara_server_last_error",
-           "ara_ep_curve_scratch_size", "ara_ep_curve"]
+           "ara_ep_curve_scratch_size", "ara_ep_curve", "ara_probe_stream_read",
+           "ara_probe_valu_lanes", "ara_probe_valu", "ara_probe_draws",
+           "ara_debug_beta_quantile_shape"]
+
+PROBE_KINDS = {"fma_f32": 0, "mul_f32": 1, "xad_u32": 2, "mulhi_u32": 3, "mad_u64_u32": 4,
+               "exp2_f32": 5, "fma_f64": 6}
 
 SERVER_MAX_RP = 16
 
@@ -105,7 +111,7 @@ class ara_server_result(C.Structure):
 class ara_run_opts(C.Structure):
     _fields_ = [("trial_begin", C.c_int64), ("trial_count", C.c_int64),
                 ("sum_mode", C.c_int32), ("ylt_dtype", C.c_int32),
-                ("tail_band", C.c_float), ("reserved", C.c_int32),
+                ("tail_band", C.c_float), ("debug_flags", C.c_int32),
                 ("d_hits", C.c_void_p), ("d_hit_chk", C.c_void_p),
                 ("d_scratch", C.c_void_p), ("scratch_bytes", C.c_size_t),
                 ("d_occ_view", C.c_void_p), ("occ_view_stride", C.c_int64)]
@@ -167,6 +173,11 @@ def lib():
         L.ara_server_last_error.restype = C.c_char_p
         L.ara_ep_curve_scratch_size.argtypes = [i64, i32, C.POINTER(sz)]
         L.ara_ep_curve.argtypes = [p, p, i32, i64, p, p, p, sz, p]
+        L.ara_probe_stream_read.argtypes = [p, p, sz, p, p]
+        L.ara_probe_valu_lanes.argtypes = [p, i32, C.POINTER(i64)]
+        L.ara_probe_valu.argtypes = [p, i32, i32, i32, p, C.POINTER(u64), p]
+        L.ara_probe_draws.argtypes = [p, i64, u64, C.c_uint32, C.c_float, C.c_float, i32, p, p]
+        L.ara_debug_beta_quantile_shape.argtypes = [p, i64, C.c_float, C.c_float, p, p, p, p, p]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is C.c_int:       # default
@@ -350,6 +361,39 @@ def ara_ep_curve(ctx, d_ylt, dtype, n, d_sorted, d_tail_mean, d_scratch, nbytes,
                                    d_scratch, nbytes, stream), "ara_ep_curve")
 
 
+def ara_probe_stream_read(ctx, d_src: int, nbytes: int, d_sink: int, stream) -> None:
+    _check(ctx, lib().ara_probe_stream_read(ctx, d_src, int(nbytes), d_sink, stream),
+           "ara_probe_stream_read")
+
+
+def ara_probe_valu_lanes(ctx, waves_per_simd: int) -> int:
+    n = C.c_int64()
+    _check(ctx, lib().ara_probe_valu_lanes(ctx, int(waves_per_simd), C.byref(n)),
+           "ara_probe_valu_lanes")
+    return int(n.value)
+
+
+def ara_probe_valu(ctx, kind: int, waves_per_simd: int, iters: int, d_out: int, stream) -> int:
+    n = C.c_uint64()
+    _check(ctx, lib().ara_probe_valu(ctx, int(kind), int(waves_per_simd), int(iters), d_out,
+                                     C.byref(n), stream), "ara_probe_valu")
+    return int(n.value)
+
+
+def ara_probe_draws(ctx, n: int, seed: int, elt_id: int, a: float, b: float,
+                    use_shape_table: bool, d_x: int, stream) -> None:
+    _check(ctx, lib().ara_probe_draws(ctx, int(n), int(seed) & 0xFFFFFFFFFFFFFFFF, int(elt_id),
+                                      float(a), float(b), 1 if use_shape_table else 0, d_x,
+                                      stream), "ara_probe_draws")
+
+
+def ara_debug_beta_quantile_shape(ctx, n: int, a: float, b: float, d_z: int, d_zc: int, d_x: int,
+                                  d_path: Optional[int], stream) -> None:
+    _check(ctx, lib().ara_debug_beta_quantile_shape(ctx, int(n), float(a), float(b), d_z, d_zc,
+                                                    d_x, d_path, stream),
+           "ara_debug_beta_quantile_shape")
+
+
 def ara_server_create(device: int, n_trials: int, n_catalogue: int, d_offsets: int,
                       d_event_ids: int, cfg: "ara_server_config"):
     h = C.c_void_p()
@@ -408,6 +452,17 @@ def _stream_handle(stream) -> Optional[int]:
         import torch
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream) or None
+
+
+def _on(stream):
+    """Context in which the convenience layer allocates the device tensors of
+    a call enqueued on ``stream``: torch's caching allocator then hands a
+    freed block of them out again only to later work of that same stream, so
+    a scratch tensor dropped on return is not reused by a call on another
+    stream while this call's kernels still run."""
+    import contextlib
+    import torch
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
 
 
 # ---- convenience layer -------------------------------------------------------
@@ -534,17 +589,30 @@ class Ara:
 
     # -- analysis ---------------------------------------------------------------
     def run(self, y: DeviceYET, p: DevicePortfolio, trial_begin: int = 0,
-            trial_count: Optional[int] = None, sum_mode: str = "naive32",
+            trial_count: Optional[int] = None, sum_mode: str = "kahan32",
             ylt_dtype: str = "f32", tail_band: float = 0.0, diagnostics: bool = False,
             out_layers=None, out_pf=None, stream=None, sync: bool = True,
             layers: bool = True, scratch=None, occ_view: bool = False,
-            occ_view_stride: Optional[int] = None):
+            occ_view_stride: Optional[int] = None, debug_flags: int = 0):
         """``ara_run``; returns dict of device tensors ``ylt`` [n_layers, n]
         and ``ylt_pf`` [n] (plus ``hits``/``hit_chk`` with diagnostics, and
-        ``occ_view`` [n_layers, occurrences of the run] on request)."""
+        ``occ_view`` [n_layers, occurrences of the run] on request).  The run's
+        scratch is a fresh tensor unless ``scratch`` is given (runs that may
+        overlap on the device need scratch of their own)."""
+        with _on(stream):
+            return self._run(y, p, trial_begin, trial_count, sum_mode, ylt_dtype, tail_band,
+                             diagnostics, out_layers, out_pf, stream, sync, layers, scratch,
+                             occ_view, occ_view_stride, debug_flags)
+
+    def _run(self, y, p, trial_begin, trial_count, sum_mode, ylt_dtype, tail_band, diagnostics,
+             out_layers, out_pf, stream, sync, layers, scratch, occ_view, occ_view_stride,
+             debug_flags):
         t = self.torch
         if trial_count is None:
             trial_count = y.n_trials - trial_begin
+        if scratch is None and p.su:
+            scratch = t.empty(ara_run_scratch_size(trial_count), dtype=t.uint8,
+                              device=self.device)
         dt = t.float64 if ylt_dtype == "f64" else t.float32
         if layers and out_layers is None:
             out_layers = t.empty((p.n_layers, trial_count), dtype=dt, device=self.device)
@@ -562,7 +630,8 @@ class Ara:
         o = ara_run_opts(trial_begin=int(trial_begin), trial_count=int(trial_count),
                          sum_mode=SUM_MODES[sum_mode],
                          ylt_dtype=ARA_F64 if ylt_dtype == "f64" else ARA_F32,
-                         tail_band=float(tail_band), reserved=0, d_hits=_ptr(hits),
+                         tail_band=float(tail_band), debug_flags=int(debug_flags),
+                         d_hits=_ptr(hits),
                          d_hit_chk=_ptr(chk), d_scratch=_ptr(scratch),
                          scratch_bytes=0 if scratch is None else scratch.numel(),
                          d_occ_view=_ptr(ov),
@@ -582,15 +651,16 @@ class Ara:
         """``ara_ep_curve``: (losses in descending order, FP64 running means or
         None) as device tensors."""
         t = self.torch
-        y = ylt.contiguous()
-        n = int(y.numel())
-        dtype = ARA_F64 if y.dtype == t.float64 else ARA_F32
-        srt = t.empty(n, dtype=y.dtype, device=self.device)
-        tm = t.empty(n, dtype=t.float64, device=self.device) if tail_mean else None
-        sz = ara_ep_curve_scratch_size(n, dtype)
-        sc = t.empty(max(1, sz), dtype=t.uint8, device=self.device)
-        ara_ep_curve(self.ctx, _ptr(y), dtype, n, _ptr(srt), _ptr(tm), _ptr(sc), sz,
-                     _stream_handle(stream))
+        with _on(stream):
+            y = ylt.contiguous()
+            n = int(y.numel())
+            dtype = ARA_F64 if y.dtype == t.float64 else ARA_F32
+            srt = t.empty(n, dtype=y.dtype, device=self.device)
+            tm = t.empty(n, dtype=t.float64, device=self.device) if tail_mean else None
+            sz = ara_ep_curve_scratch_size(n, dtype)
+            sc = t.empty(max(1, sz), dtype=t.uint8, device=self.device)
+            ara_ep_curve(self.ctx, _ptr(y), dtype, n, _ptr(srt), _ptr(tm), _ptr(sc), sz,
+                         _stream_handle(stream))
         return srt, tm
 
     def run_scratch_size(self, trial_count: int) -> int:
@@ -621,30 +691,31 @@ class Ara:
         o = ara_run_opts(trial_begin=int(trial_begin), trial_count=int(trial_count),
                          sum_mode=SUM_MODES[sum_mode],
                          ylt_dtype=ARA_F64 if ylt_dtype == "f64" else ARA_F32,
-                         tail_band=float(tail_band), reserved=0, d_hits=None, d_hit_chk=None,
+                         tail_band=float(tail_band), debug_flags=0, d_hits=None, d_hit_chk=None,
                          d_scratch=None, scratch_bytes=0)
         return o, outs, scratch
 
-    def run_batch(self, y, pfs, trial_begin=0, trial_count=None, sum_mode="naive32",
+    def run_batch(self, y, pfs, trial_begin=0, trial_count=None, sum_mode="kahan32",
                   ylt_dtype="f32", tail_band=0.0, cfg=None, outs=None, stream=None, sync=True,
                   scratch=None):
         """One persistent launch over several DevicePortfolio; returns a list of
         {"ylt", "ylt_pf"} device tensors, one per portfolio."""
-        o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, sum_mode, ylt_dtype,
-                                        tail_band, outs)
-        if scratch is not None:
-            sc = scratch
-        c = _batch_cfg(cfg)
-        s = _stream_handle(stream)
-        ara_run_batch(self.ctx, y.handle, [p.handle.value for p in pfs], o, c,
-                      [_ptr(r["ylt"]) for r in outs], [_ptr(r["ylt_pf"]) for r in outs],
-                      _ptr(sc), sc.numel(), s)
+        with _on(stream):
+            o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, sum_mode,
+                                            ylt_dtype, tail_band, outs)
+            if scratch is not None:
+                sc = scratch
+            c = _batch_cfg(cfg)
+            s = _stream_handle(stream)
+            ara_run_batch(self.ctx, y.handle, [p.handle.value for p in pfs], o, c,
+                          [_ptr(r["ylt"]) for r in outs], [_ptr(r["ylt_pf"]) for r in outs],
+                          _ptr(sc), sc.numel(), s)
         if sync:
             ara_sync_status(self.ctx, s)
         return outs
 
     def batch_autotune(self, y, pfs, trial_begin=0, trial_count=4096, stream=None):
-        o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, "naive32", "f32", 0.0,
+        o, outs, sc = self._batch_setup(y, pfs, trial_begin, trial_count, "kahan32", "f32", 0.0,
                                         None)
         best, ms = ara_batch_autotune(self.ctx, y.handle, [p.handle.value for p in pfs], o,
                                       [_ptr(r["ylt"]) for r in outs],
@@ -652,7 +723,7 @@ class Ara:
                                       _stream_handle(stream))
         return (best.trial_tile, best.waves_per_cu, best.order), ms
 
-    def batch_graph(self, y, pfs, trial_begin=0, trial_count=None, sum_mode="naive32",
+    def batch_graph(self, y, pfs, trial_begin=0, trial_count=None, sum_mode="kahan32",
                     ylt_dtype="f32", cfg=None):
         """Capture the batched run in a HIP graph; returns (graph handle, outs,
         scratch); keep outs and scratch alive while the graph exists."""
@@ -690,6 +761,17 @@ class Ara:
                                 tail_band, _ptr(x), _ptr(path), _stream_handle(stream))
         return x.cpu().numpy(), path.cpu().numpy()
 
+    def debug_beta_quantile_shape(self, a: float, b: float, z, zc, stream=None):
+        """The FP32 quantile of one shape through its shape table."""
+        t = self.torch
+        Z = t.as_tensor(np.ascontiguousarray(z, np.float64)).to(self.device)
+        ZC = t.as_tensor(np.ascontiguousarray(zc, np.float64)).to(self.device)
+        x = t.empty(Z.numel(), dtype=t.float32, device=self.device)
+        path = t.empty(Z.numel(), dtype=t.int32, device=self.device)
+        ara_debug_beta_quantile_shape(self.ctx, Z.numel(), a, b, _ptr(Z), _ptr(ZC), _ptr(x),
+                                      _ptr(path), _stream_handle(stream))
+        return x.cpu().numpy(), path.cpu().numpy()
+
 
 def evaluations(yet, pf, trial_begin: int = 0, trial_count: Optional[int] = None) -> int:
     """Trial x event x ELT evaluations of a run (zero lookups included)."""
@@ -709,7 +791,7 @@ class Server:
     max_inflight streams.  Requests are workloads.Portfolio objects."""
 
     def __init__(self, yet, device: int = 0, pool_bytes: int = 4 << 30, max_inflight: int = 2,
-                 max_batch: int = 4, sum_mode: str = "naive32", device_arrays=None):
+                 max_batch: int = 4, sum_mode: str = "kahan32", device_arrays=None):
         import torch
         self.torch = torch
         dev = torch.device("cuda", device)

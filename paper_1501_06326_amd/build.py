@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libara.so")
-SOURCES = ["ara_api.hip", "ara_kernels.hip", "ara_select.hip", "ara_serve.hip"]
+SOURCES = ["ara_api.hip", "ara_kernels.hip", "ara_select.hip", "ara_serve.hip", "ara_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("ARA_OFFLOAD_ARCH", "gfx950")

@@ -23,8 +23,6 @@ struct ara_context {
     std::string last_error;
     Status *d_status = nullptr;             // device status words
     unsigned long long *d_maxlen = nullptr;
-    void *d_run_scratch = nullptr;          // grown on demand when ara_run gets no scratch
-    size_t run_scratch_bytes = 0;
     std::set<ara_yet *> yets;
     std::set<ara_portfolio *> pfs;
     std::set<ara_graph *> graphs;
@@ -46,6 +44,24 @@ constexpr float kDefaultTailBand = 5.9604644775390625e-08f;
 
 size_t run_scratch_need(int64_t trial_count) {
     return 256 + ((size_t)(trial_count > 0 ? trial_count : 1) * sizeof(int32_t) + 255) / 256 * 256;
+}
+
+// The FP32 pass hands the trials it cannot finish to the FP64-capable pass
+// through scratch: a counter at the start, the trial list 256 bytes in.  The
+// second pass takes up to as many wavefronts as the first keeps resident
+// (7 per SIMD), each looping over the list; surplus ones find it empty.
+void su_scratch(const ara_context *ctx, SuLaunch *p, char *scr, const ara_run_opts &o) {
+    p->redo_count = (uint32_t *)scr;
+    p->redo = (int32_t *)(scr + 256);
+    const int64_t resident = (int64_t)ctx->n_cu * 4 * 7;
+    p->redo_grid = (int)(o.trial_count < resident ? (o.trial_count > 0 ? o.trial_count : 1)
+                                                  : resident);
+    if (o.debug_flags & ARA_DEBUG_QUANTILE_ONE_STEP) {
+        p->tail_band = 2.0f;       // every draw takes the FP64 quantile ...
+        p->f64_iters = 1;          // ... which may take one step
+    } else {
+        p->f64_iters = kF64QuantileIters;
+    }
 }
 
 ara_status fail(ara_context *ctx, ara_status code, const char *fmt, ...) {
@@ -71,7 +87,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Byte layout of a portfolio workspace.
 struct Layout {
-    size_t layers, elts, evoff, liveoff, rowq, rowf, row_mean, row_cfrac, row_meta, row_lnb, otab,
+    size_t layers, elts, evoff, liveoff, rowq, rowf, row_mean, row_cfrac, row_meta, row_lnb,
+        row_shape, shape_keys, shape_tab, otab,
         sp_bits, sp_rank,
         sp_vals, raw, rawfit, eltoff, dat, total;
     int64_t n_rows = 0;
@@ -127,6 +144,11 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
     L->row_cfrac = o; o += align256(sizeof(float) * (size_t)(rows ? rows : 1));
     L->row_meta = o; o += align256(sizeof(uint32_t) * (size_t)(rows ? rows : 1));
     L->row_lnb = o; o += align256(sizeof(double) * (size_t)(rows ? rows : 1));
+    const bool su = d->su_enabled != 0;
+    L->row_shape = o; o += su ? align256(sizeof(uint32_t) * (size_t)(rows ? rows : 1)) : 0;
+    L->shape_keys = o; o += su ? align256(sizeof(unsigned long long) * kShapeSlots * (nl ? nl : 1)) : 0;
+    L->shape_tab = o;
+    o += su ? align256(sizeof(float) * 2 * kShapeK * kShapeSlots * (size_t)(nl ? nl : 1)) : 0;
     const size_t nw = ((size_t)n_cat + 31) / 32;
     const bool pu = !d->su_enabled;
     L->otab = o; o += pu ? align256(sizeof(float) * (size_t)nl * n_cat) : 0;
@@ -165,6 +187,10 @@ ara_status check_status(ara_context *ctx, hipStream_t s, const char *what) {
         return fail(ctx, h.code, "%s: occurrence view stride %lld too small (trial %lld needs "
                                  "index %lld)", what, (long long)h.where[2], (long long)h.where[0],
                     (long long)h.where[1]);
+    case ARA_E_INVALID_ARG:
+        return fail(ctx, h.code, "%s: hand-over entry %lld between the passes names trial %lld "
+                                 "outside the run (scratch shared by runs that overlapped?)",
+                    what, (long long)h.where[0], (long long)h.where[1]);
     case ARA_E_NUMERIC:
         return fail(ctx, h.code, "%s: Beta quantile did not converge (trial %lld, occurrence %lld, "
                                  "elt_id %lld)", what, (long long)h.where[0], (long long)h.where[1],
@@ -175,6 +201,27 @@ ara_status check_status(ara_context *ctx, hipStream_t s, const char *what) {
 }
 
 float to_f32_term(double v) { return std::isinf(v) ? INFINITY : (float)v; }
+
+uint32_t fbits(float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, sizeof u);
+    return u;
+}
+
+// A shape table for one (a, b) in freshly allocated device memory (the two
+// diagnostics below only): key + table; the caller frees *mem.
+ara_status one_shape_table(ara_context *ctx, float a, float b, hipStream_t s, void **mem,
+                           float **tab) {
+    *mem = nullptr;
+    const size_t bytes = 256 + sizeof(float) * 2 * kShapeK;
+    ARA_HIP(ctx, hipMalloc(mem, bytes));
+    const unsigned long long key = ((unsigned long long)fbits(a) << 32) | fbits(b);
+    ARA_HIP(ctx, hipMemcpyAsync(*mem, &key, sizeof key, hipMemcpyHostToDevice, s));
+    *tab = (float *)((char *)*mem + 256);
+    ARA_HIP(ctx, launch_shape_tables((const unsigned long long *)*mem, 1, *tab, s));
+    ARA_HIP(ctx, hipStreamSynchronize(s));
+    return ARA_OK;
+}
 
 }  // namespace
 
@@ -243,7 +290,6 @@ void ara_destroy(ara_context *ctx) {
     }
     (void)hipFree(ctx->d_status);
     (void)hipFree(ctx->d_maxlen);
-    (void)hipFree(ctx->d_run_scratch);
     delete ctx;
 }
 
@@ -387,6 +433,9 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
     p->d_row_cfrac = (float *)(w + L.row_cfrac);
     p->d_row_meta = (uint32_t *)(w + L.row_meta);
     p->d_row_lnb = (double *)(w + L.row_lnb);
+    p->d_row_shape = desc->su_enabled ? (uint32_t *)(w + L.row_shape) : nullptr;
+    p->d_shape_keys = desc->su_enabled ? (unsigned long long *)(w + L.shape_keys) : nullptr;
+    p->d_shape_tab = desc->su_enabled ? (float *)(w + L.shape_tab) : nullptr;
     p->d_otab = desc->su_enabled ? nullptr : (float *)(w + L.otab);
     p->d_sp_bits = desc->su_enabled ? nullptr : (uint32_t *)(w + L.sp_bits);
     p->d_sp_rank = desc->su_enabled ? nullptr : (uint32_t *)(w + L.sp_rank);
@@ -428,20 +477,29 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
     RowFit *d_fit = (RowFit *)(w + L.rawfit);
     ARA_HIP_P(launch_fit_rows(d_raw, L.n_rows, p->su_enabled, d_fit, s));
     const size_t nwc = ((size_t)n_catalogue + 31) / 32;
+    if (p->su_enabled && L.n_rows > 0)
+        ARA_HIP_P(launch_fill_i32((int32_t *)p->d_row_shape, L.n_rows, 0, s));
     for (int l = 0; l < nl; ++l) {
+        uint32_t *liveoff_l = (uint32_t *)(w + L.liveoff) + (size_t)l * ((size_t)n_catalogue + 1);
         ARA_HIP_P(launch_build_layer(d_raw, d_fit, d_eltoff, p->d_elts, p->d_layers + l, hl[l],
                                      n_catalogue,
-                                     p->su_enabled, d_dat, p->d_evoff,
-                                     (uint32_t *)(w + L.liveoff) + (size_t)l * ((size_t)n_catalogue + 1),
+                                     p->su_enabled, d_dat, p->d_evoff, liveoff_l,
                                      p->d_rowq, p->d_rowf, p->d_row_mean,
                                      p->d_row_cfrac, p->d_row_meta, p->d_row_lnb, p->d_otab,
                                      ctx->d_status, s));
+        if (p->su_enabled)
+            ARA_HIP_P(launch_shape_collect(p->d_rowf, hl[l].row_base, liveoff_l, n_catalogue,
+                                           p->d_row_shape,
+                                           p->d_shape_keys + (size_t)l * kShapeSlots, s));
         if (!p->su_enabled)
             ARA_HIP_P(launch_build_sparse(p->d_otab + (size_t)l * n_catalogue, n_catalogue,
                                           p->d_sp_bits + (size_t)l * nwc,
                                           p->d_sp_rank + (size_t)l * (nwc + 1),
                                           p->d_sp_vals + (size_t)l * n_catalogue, p->d_layers + l, s));
     }
+    if (p->su_enabled)
+        ARA_HIP_P(launch_shape_tables(p->d_shape_keys, (int64_t)nl * kShapeSlots, p->d_shape_tab,
+                                      s));
     p->h_layers = new LayerDev[nl > 0 ? nl : 1];
     if (nl > 0)
         ARA_HIP_P(hipMemcpyAsync(p->h_layers, p->d_layers, sizeof(LayerDev) * nl,
@@ -487,12 +545,14 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
     if (o.trial_begin < 0 || o.trial_count < 0 || o.trial_begin + o.trial_count > yet->n_trials)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run: trial range [%lld, +%lld) outside the YET",
                     (long long)o.trial_begin, (long long)o.trial_count);
-    if (o.sum_mode < ARA_SUM_NAIVE32 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
+    if (o.sum_mode < 0 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
         o.ylt_dtype > ARA_F64)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run: bad sum_mode or ylt_dtype");
     if (o.trial_count > 0x7fffffff)
         return fail(ctx, ARA_E_UNSUPPORTED, "ara_run: more than 2^31 trials in one run");
     if (!(o.tail_band > 0.0f)) o.tail_band = kDefaultTailBand;
+    if (o.debug_flags & ~ARA_DEBUG_QUANTILE_ONE_STEP)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run: unknown debug flags 0x%x", o.debug_flags);
     if (o.d_occ_view && o.occ_view_stride <= 0)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run: occurrence view without a positive stride");
     if (o.trial_count == 0 || pf->n_layers == 0) {
@@ -555,6 +615,8 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
     p.row_cfrac = pf->d_row_cfrac;
     p.row_meta = pf->d_row_meta;
     p.row_lnb = pf->d_row_lnb;
+    p.shape_tab = pf->d_shape_tab;
+    p.row_shape = pf->d_row_shape;
     p.seed = pf->seed;
     p.tail_band = o.tail_band;
     p.ylt_layers = d_ylt_layers;
@@ -566,23 +628,11 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
     p.status = ctx->d_status;
     const size_t need = run_scratch_need(o.trial_count);
     char *scr = (char *)o.d_scratch;
-    if (scr) {
-        if (o.scratch_bytes < need)
-            return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_run: need %zu scratch bytes", need);
-    } else {
-        if (ctx->run_scratch_bytes < need) {
-            ARA_HIP(ctx, hipStreamSynchronize(s));
-            ARA_HIP(ctx, hipFree(ctx->d_run_scratch));
-            ctx->d_run_scratch = nullptr;
-            ctx->run_scratch_bytes = 0;
-            ARA_HIP(ctx, hipMalloc(&ctx->d_run_scratch, need));
-            ctx->run_scratch_bytes = need;
-        }
-        scr = (char *)ctx->d_run_scratch;
-    }
-    p.redo_count = (uint32_t *)scr;
-    p.redo = (int32_t *)(scr + 256);
-    p.redo_grid = ctx->n_cu * 4;
+    if (!scr || o.scratch_bytes < need)
+        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL,
+                    "ara_run: secondary uncertainty needs %zu bytes of scratch (opts->d_scratch)",
+                    need);
+    su_scratch(ctx, &p, scr, o);
     ARA_HIP(ctx, launch_su(p, o.sum_mode, f64out, s));
     return ARA_OK;
 }
@@ -692,7 +742,7 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     o.trial_count = -1;
     if (opts) o = *opts;
     if (o.trial_count < 0) o.trial_count = yet->n_trials - o.trial_begin;
-    if (o.sum_mode < ARA_SUM_NAIVE32 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
+    if (o.sum_mode < 0 || o.sum_mode > ARA_SUM_F64 || o.ylt_dtype < ARA_F32 ||
         o.ylt_dtype > ARA_F64)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: bad sum_mode or ylt_dtype");
     if (o.d_hits || o.d_hit_chk || o.d_occ_view)
@@ -734,6 +784,7 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
         b.row_cfrac = p->d_row_cfrac;
         b.row_meta = p->d_row_meta;
         b.row_lnb = p->d_row_lnb;
+        b.shape_tab = p->d_shape_tab;
         b.ylt_layers = ylt_l ? ylt_l[i] : nullptr;
         b.ylt_pf = ylt_p ? ylt_p[i] : nullptr;
         b.k0 = (uint32_t)p->seed;
@@ -935,6 +986,45 @@ ara_status ara_debug_philox(ara_context *ctx, int64_t n, const uint32_t *d_ctr, 
     return ARA_OK;
 }
 
+ara_status ara_debug_beta_quantile_shape(ara_context *ctx, int64_t n, float a, float b,
+                                         const double *d_z, const double *d_zc, float *d_x,
+                                         int32_t *d_path, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!d_z || !d_zc || !d_x)) ||
+        !(a >= kF32MinShape && a <= kF32MaxShape) || !(b >= kF32MinShape && b <= kF32MaxShape))
+        return fail(ctx, ARA_E_INVALID_ARG,
+                    "ara_debug_beta_quantile_shape: bad arguments (a, b in [1, 32])");
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    void *mem = nullptr;
+    float *tab = nullptr;
+    ara_status st = one_shape_table(ctx, a, b, s, &mem, &tab);
+    if (st != ARA_OK) {
+        (void)hipFree(mem);
+        return st;
+    }
+    // the per-entry shape arrays of the general diagnostic, all (a, b)
+    void *ab = nullptr;
+    hipError_t e = hipMalloc(&ab, sizeof(float) * 2 * (size_t)(n > 0 ? n : 1));
+    if (e == hipSuccess && n > 0) {
+        std::vector<float> h(2 * (size_t)n);
+        for (int64_t j = 0; j < n; ++j) {
+            h[(size_t)j] = a;
+            h[(size_t)(n + j)] = b;
+        }
+        e = hipMemcpyAsync(ab, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_debug_quantile(n, (const float *)ab, (const float *)ab + n, d_z, d_zc,
+                                      kDefaultTailBand, tab, d_x, d_path, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    (void)hipFree(ab);
+    (void)hipFree(mem);
+    if (e != hipSuccess)
+        return fail(ctx, ARA_E_HIP, "ara_debug_beta_quantile_shape: %s", hipGetErrorString(e));
+    return ARA_OK;
+}
+
 ara_status ara_debug_beta_quantile(ara_context *ctx, int64_t n, const float *d_a, const float *d_b,
                                    const double *d_z, const double *d_zc, float tail_band,
                                    float *d_x, int32_t *d_path, void *stream) {
@@ -943,8 +1033,78 @@ ara_status ara_debug_beta_quantile(ara_context *ctx, int64_t n, const float *d_a
         return fail(ctx, ARA_E_INVALID_ARG, "ara_debug_beta_quantile: bad arguments");
     if (!(tail_band > 0.0f)) tail_band = kDefaultTailBand;
     ARA_HIP(ctx, hipSetDevice(ctx->device));
-    ARA_HIP(ctx, launch_debug_quantile(n, d_a, d_b, d_z, d_zc, tail_band, d_x, d_path,
+    ARA_HIP(ctx, launch_debug_quantile(n, d_a, d_b, d_z, d_zc, tail_band, nullptr, d_x, d_path,
                                        (hipStream_t)stream));
+    return ARA_OK;
+}
+
+ara_status ara_probe_stream_read(ara_context *ctx, const void *d_src, size_t bytes,
+                                 uint32_t *d_sink, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!d_src || !d_sink || bytes % 16 != 0 || ((uintptr_t)d_src & 15) != 0)
+        return fail(ctx, ARA_E_INVALID_ARG,
+                    "ara_probe_stream_read: need a 16-byte aligned source and a multiple of 16 bytes");
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    ARA_HIP(ctx, launch_probe_stream(d_src, (int64_t)(bytes / 16), d_sink, ctx->n_cu,
+                                     (hipStream_t)stream));
+    return ARA_OK;
+}
+
+ara_status ara_probe_valu_lanes(ara_context *ctx, int32_t waves_per_simd, int64_t *lanes) {
+    if (!ctx || !lanes || waves_per_simd < 1 || waves_per_simd > 8) return ARA_E_INVALID_ARG;
+    *lanes = (int64_t)ctx->n_cu * waves_per_simd * 256;
+    return ARA_OK;
+}
+
+ara_status ara_probe_valu(ara_context *ctx, int32_t kind, int32_t waves_per_simd, int32_t iters,
+                          float *d_out, uint64_t *valu_instr, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (kind < ARA_PROBE_FMA_F32 || kind > ARA_PROBE_FMA_F64 || waves_per_simd < 1 ||
+        waves_per_simd > 8 || iters < 1 || !d_out)
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_probe_valu: bad arguments");
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    // one 4-wavefront block per SIMD quadruple: waves_per_simd blocks per CU
+    const int blocks = ctx->n_cu * waves_per_simd;
+    ARA_HIP(ctx, launch_probe_valu(kind, blocks, iters, d_out, (hipStream_t)stream));
+    // eight chains, one instruction per step (two for XAD and MAD_U64_U32)
+    const uint64_t per_round =
+        (kind == ARA_PROBE_XAD_U32 || kind == ARA_PROBE_MAD_U64_U32) ? 16u : 8u;
+    if (valu_instr) *valu_instr = (uint64_t)blocks * 4u * per_round * (uint64_t)iters;
+    return ARA_OK;
+}
+
+ara_status ara_probe_draws(ara_context *ctx, int64_t n, uint64_t seed, uint32_t elt_id, float a,
+                           float b, int32_t use_shape_table, float *d_x, void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && !d_x) || !(a >= kF32MinShape && a <= kF32MaxShape) ||
+        !(b >= kF32MinShape && b <= kF32MaxShape))
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_probe_draws: bad arguments (a, b in [1, 32])");
+    hipStream_t s = (hipStream_t)stream;
+    ARA_HIP(ctx, hipSetDevice(ctx->device));
+    // the row constants as the portfolio build makes them
+    const double lnb = std::lgamma((double)a) + std::lgamma((double)b) -
+                       std::lgamma((double)a + (double)b);
+    const float lnb2 = (float)(lnb * 1.4426950408889634);
+    int32_t h[2] = {0, 0};
+    int32_t *d = (int32_t *)ctx->d_maxlen;     // 8 bytes of context scratch, free between loads
+    ARA_HIP(ctx, launch_probe_row_consts(a, b, d, s));
+    ARA_HIP(ctx, hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, s));
+    ARA_HIP(ctx, hipStreamSynchronize(s));
+    if (h[0] == 0 || h[1] == 0)
+        return fail(ctx, ARA_E_UNSUPPORTED, "ara_probe_draws: shape needs the FP64 quantile");
+    void *mem = nullptr;
+    float *tab = nullptr;
+    if (use_shape_table) {
+        ara_status st = one_shape_table(ctx, a, b, s, &mem, &tab);
+        if (st != ARA_OK) {
+            (void)hipFree(mem);
+            return st;
+        }
+    }
+    hipError_t e = launch_probe_draws(n, seed, elt_id, a, b, lnb2, h[0], h[1], tab, d_x, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    if (e != hipSuccess) return fail(ctx, ARA_E_HIP, "ara_probe_draws: %s", hipGetErrorString(e));
     return ARA_OK;
 }
 

@@ -55,13 +55,15 @@ struct RowQ {
 
 // Compact record of a row that can pay, read by the fast passes with one
 // 32-byte load (one cache line): the layer's such rows are contiguous,
-// event-major.  row is the index of the same row in the per-row arrays.
+// event-major.  row is the index of the same row in the per-row arrays;
+// shape is 1 + the slot of the row's Beta shape among the layer's shape
+// tables, or 0 when the row has none.
 struct __attribute__((aligned(16))) RowF {
     float scale, a, b, lnb;
     uint32_t meta;
     float cfrac;
     uint32_t row;
-    uint32_t pad;
+    uint32_t shape;
 };
 
 // Raw host rows staged on the device for the build kernels.
@@ -91,6 +93,23 @@ constexpr int kWave = 64;
 // there); others take the FP64 path.
 constexpr float kF32MinShape = 1.0f;
 constexpr float kF32MaxShape = 32.0f;
+
+// Step limit of the FP64 quantile's bracketed iteration; a draw that has not
+// converged by then is reported as ARA_E_NUMERIC.
+constexpr int kF64QuantileIters = 400;
+
+// Beta shapes shared by many rows.  Each layer has kShapeSlots slots; the
+// first distinct (alpha, beta) pairs of its rows on the FP32 quantile path
+// take one each.  A slot holds, for each half of the draw grid (z <= 1/2 and
+// z > 1/2, with p = min(z, 1 - z)), the logit log(x / (1 - x)) of the
+// quantile x at kShapeK points evenly spaced in t = sqrt(-2 ln p) over
+// [sqrt(2 ln 2), sqrt(48 ln 2)] (p from 1/2 down to 2^-24): linear
+// interpolation in t starts the quantile within ~2.2e-4 of its root for every
+// shape of the FP32 domain, close enough for a single Halley step.
+constexpr int kShapeSlots = 16;
+constexpr int kShapeK = 128;
+constexpr double kShapeTLo = 1.1774100225154747;   // sqrt(2 ln 2)
+constexpr double kShapeTHi = 5.768107546403532;    // sqrt(48 ln 2)
 
 }  // namespace ara
 
@@ -125,6 +144,9 @@ struct ara_portfolio {
     float *d_row_cfrac;
     uint32_t *d_row_meta;
     double *d_row_lnb;
+    uint32_t *d_row_shape;     // per row: 1 + its shape slot, or 0
+    unsigned long long *d_shape_keys;   // [layer][kShapeSlots]: (alpha, beta) bits, 0 = unused
+    float *d_shape_tab;        // [layer][kShapeSlots][2][kShapeK]
     float *d_otab;
     uint32_t *d_sp_bits;       // per layer [nw]: bitmap of the non-zero otab entries
     uint32_t *d_sp_rank;       // per layer [nw + 1]: set bits before each word

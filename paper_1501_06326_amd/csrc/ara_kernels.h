@@ -53,6 +53,9 @@ struct SuLaunch {
     int32_t *redo;            // [trial_count] scratch: trials handed to the FP64-capable pass
     uint32_t *redo_count;     // scratch counter
     int redo_grid;            // blocks of the second pass
+    int32_t f64_iters;        // step limit of the FP64 quantile
+    const float *shape_tab;   // shape tables [layer][kShapeSlots][2][kShapeK]
+    const uint32_t *row_shape;   // per row: 1 + shape slot, or 0
     void *occ_view;           // optional occurrence view (see ara_run_opts)
     int64_t occ_stride;
 };
@@ -68,6 +71,7 @@ struct BatchPf {
     const float *row_cfrac;
     const uint32_t *row_meta;
     const double *row_lnb;
+    const float *shape_tab;    // shape tables [layer][kShapeSlots][2][kShapeK]
     void *ylt_layers;
     void *ylt_pf;
     uint32_t k0, k1;           // Philox key (the portfolio's seed)
@@ -119,8 +123,24 @@ hipError_t launch_scan_excl_u32(uint32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out,
                                hipStream_t s);
 hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, const double *z,
-                                 const double *zc, float tail, float *x, int32_t *path,
-                                 hipStream_t s);
+                                 const double *zc, float tail, const float *tab, float *x,
+                                 int32_t *path, hipStream_t s);
+// shape tables: the distinct shapes of one layer's paying rows into keys
+// [kShapeSlots] (rows get their slot), then the tables of n_slots slots
+hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, const uint32_t *liveoff,
+                                int32_t n_cat, uint32_t *row_shape, unsigned long long *keys,
+                                hipStream_t s);
+hipError_t launch_shape_tables(const unsigned long long *keys, int64_t n_slots, float *tab,
+                               hipStream_t s);
+
+// measurement probes (ara_probe.hip)
+hipError_t launch_probe_stream(const void *src, int64_t n16, uint32_t *sink, int n_cu,
+                               hipStream_t s);
+hipError_t launch_probe_valu(int kind, int blocks, int32_t iters, float *out, hipStream_t s);
+hipError_t launch_probe_row_consts(float a, float b, int32_t *d_out, hipStream_t s);
+hipError_t launch_probe_draws(int64_t n, uint64_t seed, uint32_t elt_id, float a, float b,
+                              float lnb2, int32_t na, int32_t nb, const float *tab, float *x,
+                              hipStream_t s);
 
 // PML / TVaR and the exceedance-probability curve (ara_select.hip)
 size_t pml_scratch_bytes(int64_t n);

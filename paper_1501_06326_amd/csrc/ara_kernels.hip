@@ -402,7 +402,7 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
                     F.meta = f | (uint32_t)j;
                     F.cfrac = cf;
                     F.row = (uint32_t)(pos - L.row_base);
-                    F.pad = 0u;
+                    F.shape = 0u;          // set by k_shape_collect
                     rowf[fpos++] = F;
                 }
                 ++pos;
@@ -608,6 +608,17 @@ __device__ __forceinline__ void pu_trials(const PuArgs &P) {
         const int64_t a = P.off[P.trial_begin + t], b = P.off[P.trial_begin + t + 1];
         const int64_t n = b - a;
         Acc<MODE> acc;
+        // the four losses of one 16-byte load: compensated summation adds
+        // their pairwise sum (error within 2 ulp of the group, so the trial's
+        // error stays a few ulp of its total whatever its length) at a
+        // quarter of the per-element cost; the other modes add them one by one
+        auto add4 = [&](const int4 q) {
+            if (MODE == ARA_SUM_KAHAN32) {
+                acc.add((look(q.x) + look(q.y)) + (look(q.z) + look(q.w)));
+            } else {
+                acc.add(look(q.x)); acc.add(look(q.y)); acc.add(look(q.z)); acc.add(look(q.w));
+            }
+        };
         // int32 elements up to the next 16-byte boundary of the event-id stream
         int64_t head = (int64_t)(((16u - ((uint32_t)(uintptr_t)(P.ev + a) & 15u)) & 15u) >> 2);
         if (head > n) head = n;
@@ -621,10 +632,10 @@ __device__ __forceinline__ void pu_trials(const PuArgs &P) {
             if (h1) q1 = ld_stream(v4 + i + 64);
             if (h2) q2 = ld_stream(v4 + i + 128);
             if (h3) q3 = ld_stream(v4 + i + 192);
-            acc.add(look(q0.x)); acc.add(look(q0.y)); acc.add(look(q0.z)); acc.add(look(q0.w));
-            if (h1) { acc.add(look(q1.x)); acc.add(look(q1.y)); acc.add(look(q1.z)); acc.add(look(q1.w)); }
-            if (h2) { acc.add(look(q2.x)); acc.add(look(q2.y)); acc.add(look(q2.z)); acc.add(look(q2.w)); }
-            if (h3) { acc.add(look(q3.x)); acc.add(look(q3.y)); acc.add(look(q3.z)); acc.add(look(q3.w)); }
+            add4(q0);
+            if (h1) add4(q1);
+            if (h2) add4(q2);
+            if (h3) add4(q3);
         }
         const int64_t done = head + 4 * n4;
         if (lane < n - done) acc.add(look(P.ev[a + done + lane]));
@@ -701,6 +712,9 @@ struct SuArgs {
     Status *status;
     int32_t *redo;            // trials (relative index) handed to the FP64-capable pass
     uint32_t *redo_count;
+    int32_t f64_iters;        // step limit of the FP64 quantile
+    const float *shape_tab;   // the portfolio's shape tables ([layer][kShapeSlots][2][kShapeK])
+    const uint32_t *row_shape;   // per row: 1 + its shape slot, or 0 (the diagnostic pass)
     void *occ_view;           // occurrence view, written by the DIAG and OCC instantiations
     int64_t occ_stride;
 };
@@ -797,7 +811,7 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                     // the row's flags and Beta parameters: one compact record in
                     // the fast passes (row indexes the paying rows), the per-row
                     // arrays in the diagnostic pass (row indexes all rows)
-                    uint32_t meta, orow;
+                    uint32_t meta, orow, shape;
                     RowQ q;
                     float cfrac;
                     if (DIAG) {
@@ -805,6 +819,7 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         q = A.rowq[row];
                         cfrac = A.row_cfrac[row];
                         orow = row;
+                        shape = A.row_shape[row];
                     } else {
                         const RowF F = A.rowf[row];
                         meta = F.meta;
@@ -814,7 +829,12 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         q.lnb = F.lnb;
                         cfrac = F.cfrac;
                         orow = (uint32_t)rb0 + F.row;
+                        shape = F.shape;
                     }
+                    // the row's shape table, when its shape has a slot
+                    const float *tab =
+                        shape ? A.shape_tab + ((size_t)l * kShapeSlots + (shape - 1u)) * 2 * kShapeK
+                              : nullptr;
                     const uint32_t ei = meta & 0xffffu;
                     // the layer's ELT record: an LDS read when the layer's records
                     // are staged (the global read is a different instruction, so the
@@ -857,7 +877,7 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         if (!need64) {
                             bool ok;
                             const float x = beta_quantile32(q.a, q.b, q.lnb, meta_na(meta),
-                                                            meta_nb(meta), z, zc, &ok);
+                                                            meta_nb(meta), z, zc, tab, &ok);
                             if (ok) loss = q.scale * x; else need64 = true;
                         }
                         if (need64) {
@@ -866,7 +886,8 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                                 hit_z<double>(meta, jI, jC, (double)cfrac, &z64, &zc64);
                                 bool ok;
                                 const double x = beta_quantile64((double)q.a, (double)q.b,
-                                                                 A.row_lnb[orow], z64, zc64, &ok);
+                                                                 A.row_lnb[orow], z64, zc64,
+                                                                 A.f64_iters, &ok);
                                 if (!ok) report(A.status, ARA_E_NUMERIC, ti, seg + kl, ed.elt_id);
                                 loss = (float)((double)q.scale * x);
                             } else {
@@ -1003,9 +1024,19 @@ __global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
     __shared__ float X[kSeg];
     __shared__ uint2 Q[kQCap];
     __shared__ EltDev El[kEltLds];
-    const uint32_t n = *A.redo_count;
-    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x)
-        su_trial<MODE, F64OUT, DIAG, true, OCC>(A, keys, (int64_t)A.redo[r], X, Q, El);
+    // the list holds at most one entry per trial of the run; an entry outside
+    // the run (scratch shared by runs that overlapped, against the contract)
+    // is reported instead of followed
+    const uint32_t cnt = *A.redo_count;
+    const uint32_t n = cnt < (uint32_t)A.trial_count ? cnt : (uint32_t)A.trial_count;
+    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const int32_t t = A.redo[r];
+        if (t < 0 || (int64_t)t >= A.trial_count) {
+            if (threadIdx.x == 0) report(A.status, ARA_E_INVALID_ARG, r, t, A.trial_count);
+            continue;
+        }
+        su_trial<MODE, F64OUT, DIAG, true, OCC>(A, keys, (int64_t)t, X, Q, El);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1045,6 +1076,9 @@ __device__ __forceinline__ void batch_view(const BatchArgs &B, int p, SuArgs &A,
     A.status = B.status;
     A.redo = nullptr;
     A.redo_count = nullptr;
+    A.f64_iters = kF64QuantileIters;
+    A.shape_tab = P.shape_tab;
+    A.row_shape = nullptr;
     A.occ_view = nullptr;
     A.occ_stride = 0;
     keys.k0 = P.k0;
@@ -1128,10 +1162,16 @@ __global__ __launch_bounds__(64) void k_ara_batch_redo(BatchArgs B) {
     const uint32_t n = *B.redo_count;
     for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
         const unsigned long long e = B.redo[r];
+        const int p = (int)(e >> 32);
+        const int64_t t = (int64_t)(e & 0xffffffffull);
+        if (p >= B.n_pf || t >= B.pfs[p].trial_count) {     // see k_ara_su_redo
+            if (threadIdx.x == 0) report(B.status, ARA_E_INVALID_ARG, r, p, t);
+            continue;
+        }
         SuArgs A;
         PhiloxKeys keys;
-        batch_view(B, (int)(e >> 32), A, keys);
-        su_trial<MODE, F64OUT, false, true>(A, keys, (int64_t)(e & 0xffffffffull), X, Q, El);
+        batch_view(B, p, A, keys);
+        su_trial<MODE, F64OUT, false, true>(A, keys, t, X, Q, El);
     }
 }
 
@@ -1152,10 +1192,12 @@ __global__ void k_debug_philox(int64_t n, const uint32_t *__restrict__ ctr, Phil
     }
 }
 
+// tab: a shape table built for every entry's (a, b) (one shape), or null
 __global__ __launch_bounds__(64) void k_debug_quantile(int64_t n, const float *__restrict__ a,
                                                        const float *__restrict__ b,
                                                        const double *__restrict__ z,
                                                        const double *__restrict__ zc, float tail,
+                                                       const float *__restrict__ tab,
                                                        float *__restrict__ x,
                                                        int32_t *__restrict__ path) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1172,13 +1214,14 @@ __global__ __launch_bounds__(64) void k_debug_quantile(int64_t n, const float *_
         if (na == 0 || nb == 0) use64 = true;
         else {
             bool ok;
-            r = beta_quantile32(A, B, (float)(lnb * 1.4426950408889634), na, nb, zf, zcf, &ok);
+            r = beta_quantile32(A, B, (float)(lnb * 1.4426950408889634), na, nb, zf, zcf, tab,
+                                &ok);
             if (!ok) use64 = true;
         }
     }
     if (use64) {
         bool ok;
-        r = (float)beta_quantile64((double)A, (double)B, lnb, z[j], zc[j], &ok);
+        r = (float)beta_quantile64((double)A, (double)B, lnb, z[j], zc[j], kF64QuantileIters, &ok);
         if (!ok) r = __builtin_nanf("");
     }
     x[j] = r;
@@ -1314,7 +1357,8 @@ static hipError_t su_dispatch2(const SuLaunch &p, hipStream_t s) {
     A.row_lnb = p.row_lnb;
     A.tail_band = p.tail_band; A.ylt_layers = p.ylt_layers; A.ylt_pf = p.ylt_pf;
     A.hits = p.hits; A.hit_chk = p.hit_chk; A.status = p.status;
-    A.redo = p.redo; A.redo_count = p.redo_count;
+    A.redo = p.redo; A.redo_count = p.redo_count; A.f64_iters = p.f64_iters;
+    A.shape_tab = p.shape_tab; A.row_shape = p.row_shape;
     A.occ_view = p.occ_view; A.occ_stride = p.occ_stride;
     const PhiloxKeys keys = philox_keys(p.seed);
     // a kernel, not hipMemsetAsync, so the sequence can be captured in a graph
@@ -1386,11 +1430,109 @@ hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, uint64_t key, uin
 }
 
 hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, const double *z,
-                                 const double *zc, float tail, float *x, int32_t *path,
-                                 hipStream_t s) {
+                                 const double *zc, float tail, const float *tab, float *x,
+                                 int32_t *path, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_debug_quantile, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, a, b,
-                       z, zc, tail, x, path);
+                       z, zc, tail, tab, x, path);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// shape tables
+// ---------------------------------------------------------------------------
+// The distinct Beta shapes of one layer's paying rows on the FP32 quantile
+// path into kShapeSlots slots, one block per layer, by a rule that depends on
+// the rows alone (so every load of a portfolio gives every row the same
+// path): each thread lists the first distinct shapes of its contiguous
+// chunk of rows in row order, thread 0 merges the lists in chunk order until
+// the slots are full, and every paying row then gets 1 + its slot, or 0, in
+// its compact record and in the per-row array.  keys[kShapeSlots] receives
+// the slots (0 = unused).
+__device__ __forceinline__ bool shape_eligible(const RowF &F) {
+    return !(F.meta & (ROW_DET | ROW_F64 | ROW_CORR));
+}
+__device__ __forceinline__ unsigned long long shape_key(const RowF &F) {
+    return ((unsigned long long)__float_as_uint(F.a) << 32) | __float_as_uint(F.b);
+}
+
+__global__ __launch_bounds__(256) void k_shape_collect(RowF *__restrict__ rowf, int64_t row_base,
+                                                       const uint32_t *__restrict__ liveoff,
+                                                       int32_t n_cat,
+                                                       uint32_t *__restrict__ row_shape,
+                                                       unsigned long long *__restrict__ keys) {
+    __shared__ unsigned long long loc[256][kShapeSlots];
+    __shared__ int locn[256];
+    __shared__ unsigned long long slot[kShapeSlots];
+    const int tid = threadIdx.x;
+    const uint32_t n = liveoff[n_cat];
+    const uint32_t per = (n + 255u) / 256u;
+    const uint32_t lo = (uint32_t)tid * per, hi = min(n, lo + per);
+    int m = 0;
+    for (uint32_t i = lo; i < hi && m < kShapeSlots; ++i) {
+        const RowF F = rowf[row_base + i];
+        if (!shape_eligible(F)) continue;
+        const unsigned long long key = shape_key(F);
+        bool seen = false;
+        for (int q = 0; q < m; ++q) seen = seen || loc[tid][q] == key;
+        if (!seen) loc[tid][m++] = key;
+    }
+    locn[tid] = m;
+    __syncthreads();
+    if (tid == 0) {
+        int ns = 0;
+        for (int t = 0; t < 256 && ns < kShapeSlots; ++t)
+            for (int q = 0; q < locn[t] && ns < kShapeSlots; ++q) {
+                const unsigned long long key = loc[t][q];
+                bool seen = false;
+                for (int k = 0; k < ns; ++k) seen = seen || slot[k] == key;
+                if (!seen) slot[ns++] = key;
+            }
+        for (int k = ns; k < kShapeSlots; ++k) slot[k] = 0ull;
+    }
+    __syncthreads();
+    for (uint32_t i = (uint32_t)tid; i < n; i += 256u) {
+        RowF &F = rowf[row_base + i];
+        uint32_t sh = 0;
+        if (shape_eligible(F)) {
+            const unsigned long long key = shape_key(F);
+            for (int k = 0; k < kShapeSlots; ++k)
+                if (slot[k] == key) {
+                    sh = (uint32_t)k + 1u;
+                    break;
+                }
+        }
+        F.shape = sh;
+        row_shape[row_base + F.row] = sh;
+    }
+    if (tid < kShapeSlots) keys[tid] = slot[tid];
+}
+
+// The tables of the used slots: one block per slot, one thread per point.
+__global__ __launch_bounds__(2 * kShapeK) void k_shape_tables(const unsigned long long *__restrict__ keys,
+                                                              float *__restrict__ tab) {
+    const unsigned long long key = keys[blockIdx.x];
+    if (key == 0ull) return;
+    const double a = (double)__uint_as_float((uint32_t)(key >> 32));
+    const double b = (double)__uint_as_float((uint32_t)key);
+    const double lnb = lgamma(a) + lgamma(b) - lgamma(a + b);
+    const int upper = threadIdx.x / kShapeK, k = threadIdx.x % kShapeK;
+    tab[(size_t)blockIdx.x * 2 * kShapeK + threadIdx.x] = shape_table_logit(a, b, lnb, upper, k);
+}
+
+hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, const uint32_t *liveoff,
+                                int32_t n_cat, uint32_t *row_shape, unsigned long long *keys,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_shape_collect, dim3(1), dim3(256), 0, s, rowf, row_base, liveoff, n_cat,
+                       row_shape, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_shape_tables(const unsigned long long *keys, int64_t n_slots, float *tab,
+                               hipStream_t s) {
+    if (n_slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shape_tables, dim3((unsigned)n_slots), dim3(2 * kShapeK), 0, s, keys,
+                       tab);
     return hipGetLastError();
 }
 

@@ -184,6 +184,24 @@ __device__ __forceinline__ float beta_guess32(float a, float b, float z, float z
     return a * rcp_f(a + b * __expf(2.0f * w));
 }
 
+// Starting point from a shape table (the layout is described with
+// kShapeSlots): the logit of the quantile, interpolated linearly in
+// t = sqrt(-2 ln p) between the two table points around the draw, on the
+// table half of its z.  z is an odd multiple of 2^-24, so p = min(z, 1 - z)
+// lies in [2^-24, 1/2) and t inside the table's range.
+__device__ __forceinline__ float shape_guess_logit(const float *tab, float z, float zc) {
+    const bool upper = z > 0.5f;
+    const float p = upper ? zc : z;
+    const float t = sqrtf(-2.0f * __logf(p));
+    const float inv_h = (float)((kShapeK - 1) / (kShapeTHi - kShapeTLo));
+    const float u = fminf(fmaxf((t - (float)kShapeTLo) * inv_h, 0.0f), (float)(kShapeK - 1));
+    const int i = min((int)u, kShapeK - 2);
+    const float f = u - (float)i;
+    const float *T = tab + (upper ? kShapeK : 0) + i;
+    const float l0 = T[0], l1 = T[1];
+    return fmaf(f, l1 - l0, l0);
+}
+
 // I_x(a,b) (*I) and 1 - I_x(a,b) (*Ic), each on the side where it is
 // accurate, and the prefactor x^a (1-x)^b / B(a,b) (*front; the density is
 // front / (x (1-x))); lnb2 = log2 B(a, b); na / nb the continued-fraction
@@ -219,15 +237,31 @@ __device__ __forceinline__ void beta_inc32(float a, float b, float lnb2, int na,
 // step^3); a lane keeps the iterate of its own first such step, so its
 // result does not depend on how many iterations the wavefront runs.  Returns
 // false in *ok if it did not converge (the caller then uses the FP64 path).
+// With a shape table (tab, the row's slot; null without) the start comes
+// from the table instead, within ~2.2e-4 of the root: the first iteration
+// then takes every term and its step already decides convergence, so one
+// Halley step is the usual cost.  Whether a lane has a table depends on its
+// row only, so its result still does not depend on the lanes beside it.
 __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, int na, int nb,
-                                                 float z, float zc, bool *ok) {
-    float x0 = beta_guess32(a, b, z, zc);
-    const bool mirror = x0 > 0.5f;
+                                                 float z, float zc, const float *tab, bool *ok) {
+    const bool full0 = tab != nullptr;
+    float x0;
+    bool mirror;
+    if (full0) {
+        // the small side of the root straight from the logit L = ln(x/(1-x)):
+        // x = 1/(1+e^-L) = 1/(1+e^|L|) when L <= 0, else 1 - x = 1/(1+e^L)
+        const float L = shape_guess_logit(tab, z, zc);
+        mirror = L > 0.0f;
+        x0 = rcp_f(1.0f + __expf(fabsf(L)));
+    } else {
+        x0 = beta_guess32(a, b, z, zc);
+        mirror = x0 > 0.5f;
+        if (mirror) x0 = 1.0f - x0;
+    }
     float A = a, B = b, Z = z, ZC = zc;
     int NA = na, NB = nb;
     if (mirror) {
         A = b; B = a; Z = zc; ZC = z; NA = nb; NB = na;
-        x0 = 1.0f - x0;
     }
     // bound of both branches' term counts over the active lanes only (a
     // shuffle would also read the registers of inactive lanes): bitwise
@@ -246,9 +280,10 @@ __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, i
     const float am1 = A - 1.0f, bm1 = B - 1.0f;
     bool conv = false;
     float xf = x;          // the lane's answer: its iterate at its own first convergence
+    const int nt0 = __any(full0) ? nmax : nhalf;
     for (int it = 0; it < 6; ++it) {
-        const int nt = it == 0 ? nhalf : nmax;
-        const int nown = it == 0 ? nh : nmax;
+        const int nt = it == 0 ? nt0 : nmax;
+        const int nown = (it == 0 && !full0) ? nh : nmax;
         float I, Ic, front;
         beta_inc32(A, B, lnb2, min(NA, nown), min(NB, nown), nt, x, &I, &Ic, &front);
         const float r = lower ? (I - Z) : (ZC - Ic);
@@ -262,7 +297,7 @@ __device__ __forceinline__ float beta_quantile32(float a, float b, float lnb2, i
         if (!(xn < 1.0f)) xn = 0.5f * (x + 1.0f);
         if (!conv) {
             xf = xn;
-            conv = it > 0 && fabsf(xn - x) <= 9.765625e-4f * xn;
+            conv = (it > 0 || full0) && fabsf(xn - x) <= 9.765625e-4f * xn;
         }
         x = xn;
         if (__all(conv)) break;
@@ -322,12 +357,12 @@ __device__ inline void beta_inc64(double a, double b, double lnb, double x, doub
 // bracket); a step leaving the bracket falls back to bisection, geometric
 // while the bracket spans decades.  Returns false in *ok on failure.
 __device__ inline double beta_solve64(double a, double b, double lnb, double z, double zc,
-                                      double x, double hi0, bool *ok) {
+                                      double x, double hi0, int max_iter, bool *ok) {
     const bool lower = z <= zc;
     double lo = 0.0, hi = hi0;
     if (!(x > 0.0 && x < hi)) x = 0.5 * hi;
     *ok = false;
-    for (int it = 0; it < 400; ++it) {
+    for (int it = 0; it < max_iter; ++it) {
         double I, Ic, ld;
         beta_inc64(a, b, lnb, x, &I, &Ic, &ld);
         const double r = lower ? (I - z) : (zc - Ic);
@@ -354,9 +389,9 @@ __device__ inline double beta_solve64(double a, double b, double lnb, double z, 
 
 // FP64 quantile (any shape a, b > 0; lnb = ln B(a, b)): the root side is
 // chosen from I_{1/2}(a, b), the small side solved, the other recovered by
-// 1 - y.
+// 1 - y; at most max_iter steps.
 __device__ inline double beta_quantile64(double a, double b, double lnb, double z, double zc,
-                                        bool *ok) {
+                                        int max_iter, bool *ok) {
     double Ih, Ihc, ld;
     beta_inc64(a, b, lnb, 0.5, &Ih, &Ihc, &ld);
     const bool root_low = (z <= zc) ? (z <= Ih) : (zc >= Ihc);
@@ -366,10 +401,24 @@ __device__ inline double beta_quantile64(double a, double b, double lnb, double 
     // I_x ~ x^A / (A B(A, B)), capped inside the bracket
     double x = exp((log(Z) + log(A) + lnb) / A);
     if (!(x < 0.5)) x = 0.25;
-    double y = beta_solve64(A, B, lnb, Z, ZC, x, 0.5, ok);
+    double y = beta_solve64(A, B, lnb, Z, ZC, x, 0.5, max_iter, ok);
     if (y == 0.0) *ok = true;    // root below the smallest double
     return root_low ? y : 1.0 - y;
 }
 
-}  // namespace ara
+// One point of a shape table (see kShapeSlots): the logit of
+// I^-1(z; a, b) at point k of half `upper` (z = p, or z = 1 - p with the
+// complement p exact), solved in FP64 on both sides of the root so the
+// logit keeps its precision in both tails.
+__device__ inline float shape_table_logit(double a, double b, double lnb, int upper, int k) {
+    const double t = kShapeTLo + (kShapeTHi - kShapeTLo) * (double)k / (double)(kShapeK - 1);
+    const double p = exp(-0.5 * t * t);
+    const double z = upper ? 1.0 - p : p, zc = upper ? p : 1.0 - p;
+    bool ok1, ok2;
+    const double x = beta_quantile64(a, b, lnb, z, zc, kF64QuantileIters, &ok1);
+    const double y = beta_quantile64(b, a, lnb, zc, z, kF64QuantileIters, &ok2);   // 1 - x
+    const double L = x <= 0.5 ? log(x) - log1p(-x) : log1p(-y) - log(y);
+    return (float)L;
+}
 
+}  // namespace ara

@@ -802,3 +802,26 @@ def test_betaincinv_near_bernoulli_brackets(a, b):
         assert abs(xi + xci - 1.0) <= 2.3e-16
     # the bands next to the mass split give roots inside the double range
     assert n_inner >= 4
+
+
+def test_oracle_matches_its_stored_full_results():
+    """tests/golden/oracle_full.json (written by make_oracle_full.py from the
+    oracle and the input generators) still matches the oracle: a sample of
+    its stored trials recomputed here, at 1e-12 of the trial's gross loss."""
+    from pathlib import Path
+    from workloads import config_full, full_portfolio
+    gold = json.loads((Path(__file__).parent / "golden" / "oracle_full.json").read_text())
+    w = config_full(n_trials=gold["n_trials"], with_times=False)
+    assert w.yet.n_occ == gold["n_occurrences"]
+    assert int(w.yet.event_ids.sum(dtype=np.int64)) == gold["event_id_sum"]
+    for case, pf in (("su", w.portfolio), ("pu", full_portfolio(su=False))):
+        g = gold["cases"][case]
+        idx = g["top_index"][:40] + g["sample_index"][::100]
+        ref_y = np.array(g["top_y"][:40] + g["sample_y"][::100])
+        ref_g = np.array(g["top_gross"][:40] + g["sample_gross"][::100])
+        r = O.run_ara(w.yet, pf, trials=idx)
+        assert np.all(np.abs(r["ylt_pf"] - ref_y) <= 1e-12 * np.maximum(ref_g, 1.0))
+        assert np.allclose(r["gross"][0], ref_g, rtol=1e-9)
+    # the primary-uncertainty case looks up the same rows: equal lookup counts
+    assert gold["cases"]["su"]["hits_total"] == gold["cases"]["pu"]["hits_total"]
+    assert gold["cases"]["su"]["hit_chk_total"] == gold["cases"]["pu"]["hit_chk_total"]
