@@ -213,6 +213,22 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
  * trials handed from the FP32 pass to the FP64-capable pass). */
 ara_status ara_run_scratch_size(int64_t trial_count, size_t *bytes);
 
+/* ara_run for callers that cannot allocate device memory at all (code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc): the
+ * same run and the same results as ara_run, but the hand-over scratch is a
+ * device array the library holds on every GPU it runs on, for the life of
+ * the process (ARA_STATIC_MAX_TRIALS x 4 + 256 bytes, 16 MiB), so
+ * opts->d_scratch is ignored and the call allocates nothing; the caller still
+ * passes the inputs and outputs.  A run of more than ARA_STATIC_MAX_TRIALS
+ * trials fails with ARA_E_WORKSPACE_TOO_SMALL.  Every call on one GPU
+ * shares that array (the counter is cleared by a kernel at the start of each
+ * call): calls that overlap in time on one GPU -- on two streams, or from two
+ * contexts of the same device -- race and must be serialised by the caller.
+ * Asynchronous, as ara_run. */
+#define ARA_STATIC_MAX_TRIALS (1 << 22)
+ara_status ara_run_static(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                          const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
+                          void *stream);
 
 /* Synchronises the stream and reports ARA_E_NUMERIC (with the first failing
  * trial, occurrence and elt_id in the message) if a run since the last call

@@ -45,7 +45,7 @@ EXPORTS = ["ara_create", "ara_destroy", "ara_status_string", "ara_last_error", "
            "ara_server_release", "ara_server_destroy", "ara_server_last_error",
            "ara_ep_curve_scratch_size", "ara_ep_curve", "ara_probe_stream_read",
            "ara_probe_valu_lanes", "ara_probe_valu", "ara_probe_draws",
-           "ara_debug_beta_quantile_shape"]
+           "ara_debug_beta_quantile_shape", "ara_run_static"]
 
 PROBE_KINDS = {"fma_f32": 0, "mul_f32": 1, "xad_u32": 2, "mulhi_u32": 3, "mad_u64_u32": 4,
                "exp2_f32": 5, "fma_f64": 6}
@@ -144,6 +144,7 @@ def lib():
                                          C.POINTER(p)]
         L.ara_free_portfolio.argtypes = [p, p]
         L.ara_run.argtypes = [p, p, p, C.POINTER(ara_run_opts), p, p, p]
+        L.ara_run_static.argtypes = [p, p, p, C.POINTER(ara_run_opts), p, p, p]
         L.ara_run_scratch_size.argtypes = [i64, C.POINTER(sz)]
         L.ara_sync_status.argtypes = [p, p]
         L.ara_pml_tvar_scratch_size.argtypes = [i64, C.POINTER(sz)]
@@ -248,6 +249,15 @@ def ara_run(ctx, yet, pf, opts: "ara_run_opts", d_ylt_layers: Optional[int],
             d_ylt_portfolio: Optional[int], stream: Optional[int]) -> None:
     _check(ctx, lib().ara_run(ctx, yet, pf, C.byref(opts), d_ylt_layers, d_ylt_portfolio, stream),
            "ara_run")
+
+
+ARA_STATIC_MAX_TRIALS = 1 << 22
+
+
+def ara_run_static(ctx, yet, pf, opts: "ara_run_opts", d_ylt_layers: Optional[int],
+                   d_ylt_portfolio: Optional[int], stream: Optional[int]) -> None:
+    _check(ctx, lib().ara_run_static(ctx, yet, pf, C.byref(opts), d_ylt_layers, d_ylt_portfolio,
+                                     stream), "ara_run_static")
 
 
 def ara_run_scratch_size(trial_count: int) -> int:

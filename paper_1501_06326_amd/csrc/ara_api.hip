@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -17,9 +18,18 @@
 
 using namespace ara;
 
+// Scratch of ara_run_static: the hand-over from the FP32 pass to the
+// FP64-capable pass (a counter, then one trial index per trial) for up to
+// ARA_STATIC_MAX_TRIALS trials, in a device array each GPU holds for the life
+// of the process.  Host code reaches it only through the address
+// hipGetSymbolAddress gives for the current device (static_scratch_address).
+constexpr size_t kStaticScratchBytes = 256 + sizeof(int32_t) * (size_t)ARA_STATIC_MAX_TRIALS;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 struct ara_context {
     int device = 0;
     int n_cu = 0;
+    void *d_static_scratch = nullptr;       // this device's copy of `scratch`
     std::string last_error;
     Status *d_status = nullptr;             // device status words
     unsigned long long *d_maxlen = nullptr;
@@ -248,6 +258,26 @@ const char *ara_last_error(const ara_context *ctx) {
     return ctx ? ctx->last_error.c_str() : "no context";
 }
 
+namespace {
+// The device address of `scratch` on each device, looked up once per device
+// with that device current.
+std::mutex g_static_mu;
+void *g_static_addr[256] = {};
+
+hipError_t static_scratch_address(int device, void **addr) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (device < 0 || device >= 256) return hipErrorInvalidDevice;
+    if (!g_static_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_addr[device] = p;
+    }
+    *addr = g_static_addr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 ara_status ara_create(int hip_device, ara_context **out) {
     if (!out) return ARA_E_INVALID_ARG;
     *out = nullptr;
@@ -263,6 +293,10 @@ ara_status ara_create(int hip_device, ara_context **out) {
         return ARA_E_HIP;
     }
     ctx->n_cu = prop.multiProcessorCount;
+    if (static_scratch_address(hip_device, &ctx->d_static_scratch) != hipSuccess) {
+        delete ctx;
+        return ARA_E_HIP;
+    }
     if (hipMalloc((void **)&ctx->d_status, sizeof(Status)) != hipSuccess ||
         hipMalloc((void **)&ctx->d_maxlen, sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(ctx->d_status, 0, sizeof(Status)) != hipSuccess) {
@@ -527,9 +561,14 @@ ara_status ara_free_portfolio(ara_context *ctx, ara_portfolio *pf) {
     return ARA_OK;
 }
 
-ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
-                   const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
-                   void *stream) {
+}  // extern "C"
+
+namespace {
+// ara_run and ara_run_static: the same run, with the hand-over scratch of
+// the caller (opts->d_scratch) or the library's static array.
+ara_status run_impl(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                    const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
+                    void *stream, bool static_scratch) {
     if (!ctx) return ARA_E_INVALID_ARG;
     if (!yet || !pf || !ctx->yets.count(const_cast<ara_yet *>(yet)) ||
         !ctx->pfs.count(const_cast<ara_portfolio *>(pf)))
@@ -628,13 +667,44 @@ ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf
     p.status = ctx->d_status;
     const size_t need = run_scratch_need(o.trial_count);
     char *scr = (char *)o.d_scratch;
-    if (!scr || o.scratch_bytes < need)
+    if (static_scratch) {
+        scr = (char *)ctx->d_static_scratch;
+    } else if (!scr || o.scratch_bytes < need) {
         return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL,
                     "ara_run: secondary uncertainty needs %zu bytes of scratch (opts->d_scratch)",
                     need);
+    }
     su_scratch(ctx, &p, scr, o);
     ARA_HIP(ctx, launch_su(p, o.sum_mode, f64out, s));
     return ARA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ara_status ara_run(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                   const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
+                   void *stream) {
+    return run_impl(ctx, yet, pf, opts, d_ylt_layers, d_ylt_portfolio, stream, false);
+}
+
+ara_status ara_run_static(ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                          const ara_run_opts *opts, void *d_ylt_layers, void *d_ylt_portfolio,
+                          void *stream) {
+    if (!ctx) return ARA_E_INVALID_ARG;
+    if (!yet || !ctx->yets.count(const_cast<ara_yet *>(yet)))
+        return fail(ctx, ARA_E_INVALID_ARG, "ara_run_static: unknown YET handle");
+    int64_t count = -1, begin = 0;
+    if (opts) {
+        count = opts->trial_count;
+        begin = opts->trial_begin;
+    }
+    if (count < 0) count = yet->n_trials - begin;
+    if (count > (int64_t)ARA_STATIC_MAX_TRIALS)
+        return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL,
+                    "ara_run_static: %lld trials exceed the static scratch (at most %d per call)",
+                    (long long)count, (int)ARA_STATIC_MAX_TRIALS);
+    return run_impl(ctx, yet, pf, opts, d_ylt_layers, d_ylt_portfolio, stream, true);
 }
 
 ara_status ara_run_scratch_size(int64_t trial_count, size_t *bytes) {
