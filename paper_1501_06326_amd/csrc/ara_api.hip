@@ -74,6 +74,14 @@ void su_scratch(const ara_context *ctx, SuLaunch *p, char *scr, const ara_run_op
     }
 }
 
+// The primary-uncertainty pass of one portfolio over trials [begin, begin +
+// count): per layer, the gather-sum over the per-event occurrence-loss table
+// (ara_run, and the primary-uncertainty portfolios of a batch).
+hipError_t enqueue_pu(const ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                      int64_t begin, int64_t count, int32_t sum_mode, bool f64out,
+                      void *ylt_layers, void *ylt_pf, void *occ_view, int64_t occ_stride,
+                      Status *status, hipStream_t s);
+
 ara_status fail(ara_context *ctx, ara_status code, const char *fmt, ...) {
     if (ctx) {
         char buf[512];
@@ -171,6 +179,42 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
     L->dat = o; o += align256(sizeof(int32_t) * (size_t)(mx ? mx : 1) * n_cat);
     L->total = o;
     return ARA_OK;
+}
+
+hipError_t enqueue_pu(const ara_context *ctx, const ara_yet *yet, const ara_portfolio *pf,
+                      int64_t begin, int64_t count, int32_t sum_mode, bool f64out,
+                      void *ylt_layers, void *ylt_pf, void *occ_view, int64_t occ_stride,
+                      Status *status, hipStream_t s) {
+    const size_t nwc = ((size_t)pf->n_catalogue + 31) / 32;
+    for (int l = 0; l < pf->n_layers; ++l) {
+        PuLaunch p;
+        p.off = yet->d_off;
+        p.ev = yet->d_ev;
+        p.trial_begin = begin;
+        p.trial_count = count;
+        p.otab = pf->d_otab + (int64_t)l * pf->n_catalogue;
+        p.sp_bits = pf->d_sp_bits + (size_t)l * nwc;
+        p.sp_rank = pf->d_sp_rank + (size_t)l * (nwc + 1);
+        p.sp_vals = pf->d_sp_vals + (size_t)l * pf->n_catalogue;
+        p.nnz = pf->h_layers[l].nnz;
+        p.n_cat = pf->n_catalogue;
+        p.agg_r = pf->h_layers[l].agg_r;
+        p.agg_l = pf->h_layers[l].agg_l;
+        p.layer = l;
+        p.ylt_layers = ylt_layers;
+        p.ylt_pf = ylt_pf;
+        p.accumulate_pf = l > 0;
+        p.occ_view = occ_view;
+        p.occ_stride = occ_stride;
+        p.status = status;
+        // blocks of 16 wavefronts, two resident per CU (LDS table <= 60 KB)
+        const int64_t blocks = (count + 15) / 16;
+        const int64_t g = blocks < (int64_t)ctx->n_cu * 2 ? blocks : (int64_t)ctx->n_cu * 2;
+        p.grid = (int)(g < 1 ? 1 : g);
+        const hipError_t e = launch_pu(p, sum_mode, f64out, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 ara_status check_status(ara_context *ctx, hipStream_t s, const char *what) {
@@ -609,34 +653,9 @@ ara_status run_impl(ara_context *ctx, const ara_yet *yet, const ara_portfolio *p
         if (o.d_hits || o.d_hit_chk)
             return fail(ctx, ARA_E_UNSUPPORTED,
                         "ara_run: hit diagnostics need a portfolio with secondary uncertainty");
-        for (int l = 0; l < pf->n_layers; ++l) {
-            PuLaunch p;
-            p.off = yet->d_off;
-            p.ev = yet->d_ev;
-            p.trial_begin = o.trial_begin;
-            p.trial_count = o.trial_count;
-            const size_t nwc = ((size_t)pf->n_catalogue + 31) / 32;
-            p.otab = pf->d_otab + (int64_t)l * pf->n_catalogue;
-            p.sp_bits = pf->d_sp_bits + (size_t)l * nwc;
-            p.sp_rank = pf->d_sp_rank + (size_t)l * (nwc + 1);
-            p.sp_vals = pf->d_sp_vals + (size_t)l * pf->n_catalogue;
-            p.nnz = pf->h_layers[l].nnz;
-            p.n_cat = pf->n_catalogue;
-            p.agg_r = pf->h_layers[l].agg_r;
-            p.agg_l = pf->h_layers[l].agg_l;
-            p.layer = l;
-            p.ylt_layers = d_ylt_layers;
-            p.ylt_pf = d_ylt_portfolio;
-            p.accumulate_pf = l > 0;
-            p.occ_view = o.d_occ_view;
-            p.occ_stride = o.occ_view_stride;
-            p.status = ctx->d_status;
-            // blocks of 16 wavefronts, two resident per CU (LDS table <= 60 KB)
-            int64_t blocks = (o.trial_count + 15) / 16;
-            int64_t g = blocks < (int64_t)ctx->n_cu * 2 ? blocks : (int64_t)ctx->n_cu * 2;
-            p.grid = (int)(g < 1 ? 1 : g);
-            ARA_HIP(ctx, launch_pu(p, o.sum_mode, f64out, s));
-        }
+        ARA_HIP(ctx, enqueue_pu(ctx, yet, pf, o.trial_begin, o.trial_count, o.sum_mode, f64out,
+                                d_ylt_layers, d_ylt_portfolio, o.d_occ_view, o.occ_view_stride,
+                                ctx->d_status, s));
         return ARA_OK;
     }
     SuLaunch p;
