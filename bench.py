@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--oracle-trials", type=int, default=3000, help="precision mode")
     ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
     ap.add_argument("--graph", action="store_true", help="batched mode: also time a graph replay")
+    ap.add_argument("--pu", action="store_true",
+                    help="batched mode: the portfolios without secondary uncertainty")
     ap.add_argument("--requests", type=int, default=2000, help="served mode: requests per load")
     ap.add_argument("--loads", default="0.5,0.8,0.95,1.5",
                     help="served mode: offered loads as fractions of one-at-a-time capacity")
@@ -510,11 +512,12 @@ def bench_batched(args):
     yet = _full_yet(args.trials)
     n = yet.n_trials
     t0 = time.time()
-    pfs = batched_portfolios(args.portfolios)
+    pfs = batched_portfolios(args.portfolios, su=not args.pu)
     log(f"generated {len(pfs)} portfolios, {sum(p.n_elts for p in pfs)} ELTs "
         f"in {time.time() - t0:.1f}s")
     evals = sum(evaluations(yet, p) for p in pfs)
     ara = Ara(0)
+    min_bytes = 4 * yet.n_occ + 8 * (n + 1)
     dev = ara.device
     off = torch.from_numpy(yet.offsets).to(dev)
     ev = torch.from_numpy(yet.event_ids).to(dev)
@@ -558,7 +561,8 @@ def bench_batched(args):
     identical = all(torch.equal(a["ylt"], b["ylt"]) and torch.equal(a["ylt_pf"], b["ylt_pf"])
                     for a, b in zip(outs, seq))
     result = {
-        "metric": "batched trial*event*ELT evaluations/s (64 portfolios on the 1M-trial YET)",
+        "metric": "batched trial*event*ELT evaluations/s (64 portfolios on the 1M-trial YET"
+                  + (", primary uncertainty)" if args.pu else ")"),
         "value": evals / (bat_ms / 1e3), "unit": "evaluations/s", "n_gpus": 1,
         "ms_per_step": bat_ms, "higher_is_better": True, "dtype": "f32",
         "data": "synthetic (seeded numpy generator; lognormal ELT means)",
@@ -571,6 +575,9 @@ def bench_batched(args):
         "sequential": {"ms": seq_ms, "evaluations_per_s": evals / (seq_ms / 1e3)},
         "speedup_vs_sequential": seq_ms / bat_ms,
         "batched_equals_sequential": identical,
+        # the least a batch must read: the YET's event ids and offsets once
+        "hbm": {"min_bytes": min_bytes, "gbs": min_bytes / (bat_ms / 1e3) / 1e9,
+                "frac_of_peak": min_bytes / (bat_ms / 1e3) / 1e9 / PEAK_HBM_GBS},
     }
     if args.graph:
         g, gouts, gsc = ara.batch_graph(y, dps, cfg=cfg)
@@ -581,6 +588,7 @@ def bench_batched(args):
         e[1].record(stream)
         torch.cuda.synchronize()
         result["graph_ms"] = e[0].elapsed_time(e[1])
+        result["graph_evaluations_per_s"] = evals / (result["graph_ms"] / 1e3)
         result["graph_equals_eager"] = all(torch.equal(a["ylt_pf"], b["ylt_pf"])
                                            for a, b in zip(gouts, outs))
         ara.graph_destroy(g)

@@ -243,10 +243,11 @@ ara_status ara_sync_status(ara_context *ctx, void *stream);
  * caches, the better order when the draws dominate) or trial-major (the
  * portfolios of one tile together: the tile's event ids are read once for all
  * of them, the better order for primary-uncertainty batches, which are bound
- * by memory traffic).  Results are bit-identical to running each secondary-
- * uncertainty portfolio alone with ara_run; primary-uncertainty portfolios
- * take the per-occurrence path, whose trial sum is ordered differently from
- * ara_run's, and agree with it to FP32 rounding.  d_ylt_layers /
+ * by memory traffic).  Results are bit-identical to running each portfolio
+ * alone with ara_run: the secondary-uncertainty portfolios share the one
+ * launch, and each primary-uncertainty portfolio runs ara_run's per-event
+ * table pass after it on the same stream (captured with it by
+ * ara_batch_graph_create).  d_ylt_layers /
  * d_ylt_portfolio are host arrays of n_portfolios device pointers (entries
  * may be NULL), laid out as for ara_run over opts->trial_count trials.
  * opts->d_hits / d_hit_chk must be NULL; its d_scratch is not used (the batch
@@ -307,9 +308,9 @@ ara_status ara_graph_destroy(ara_context *ctx, ara_graph *graph);
  * A request's result does not depend on what it was batched with: it is bit
  * for bit the result of the same request submitted alone (the draws are keyed
  * by trial, occurrence and ELT id, and each trial is summed by one wavefront).
- * Secondary-uncertainty portfolios also equal ara_run bit for bit; primary-
- * uncertainty ones take the batched per-occurrence path and agree with
- * ara_run to FP32 rounding.  The server creates one context per stream on
+ * It also equals ara_run over the same trials bit for bit (primary-
+ * uncertainty portfolios run ara_run's per-event table pass).  The server
+ * creates one context per stream on
  * hip_device; the YET arrays and the pool are borrowed and must outlive the
  * server.  A request that fails validation fails alone (its result carries
  * the status; ara_server_last_error gives the message of the last failure). */

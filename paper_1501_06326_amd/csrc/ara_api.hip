@@ -810,10 +810,19 @@ size_t batch_need(int32_t n, int64_t total_trials) {
     return batch_redo_off(n) + sizeof(unsigned long long) * (size_t)(total_trials > 0 ? total_trials : 1);
 }
 
+// A primary-uncertainty portfolio of a batch: it runs the per-event table
+// pass of ara_run after the batched launch, on the same stream.
+struct PuItem {
+    const ara_portfolio *pf;
+    int64_t begin, count;
+    void *ylt_layers, *ylt_pf;
+};
+
 struct BatchPlan {
     BatchArgs B;
     int grid, redo_grid, mode;
     bool f64out;
+    std::vector<PuItem> pu;
 };
 
 // Validate a batch and upload its portfolio table.  ranges: per portfolio
@@ -851,7 +860,9 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     if (ranges && c.order == ARA_BATCH_TRIAL_MAJOR)
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: trial-major order needs one trial range");
     int64_t total = 0, items = 0;
-    std::vector<BatchPf> h((size_t)n);
+    std::vector<BatchPf> h;
+    h.reserve((size_t)n);
+    plan->pu.clear();
     for (int32_t i = 0; i < n; ++i) {
         const int64_t tb = ranges ? ranges[2 * i] : o.trial_begin;
         const int64_t tc = ranges ? ranges[2 * i + 1] : o.trial_count;
@@ -863,7 +874,12 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
             return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: unknown portfolio %d", i);
         if (p->n_catalogue != yet->n_catalogue)
             return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: portfolio %d catalogue mismatch", i);
-        BatchPf &b = h[(size_t)i];
+        if (!p->su_enabled) {
+            plan->pu.push_back({p, tb, tc, ylt_l ? ylt_l[i] : nullptr, ylt_p ? ylt_p[i] : nullptr});
+            continue;
+        }
+        h.emplace_back();
+        BatchPf &b = h.back();
         b.layers = p->d_layers;
         b.elts = p->d_elts;
         b.evoff = p->d_evoff;
@@ -890,8 +906,10 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     if (!scratch || bytes < need)
         return fail(ctx, ARA_E_WORKSPACE_TOO_SMALL, "ara_run_batch: need %zu scratch bytes", need);
     char *sc = (char *)scratch;
-    ARA_HIP(ctx, hipMemcpyAsync(sc + batch_pf_off(), h.data(), sizeof(BatchPf) * h.size(),
-                                hipMemcpyHostToDevice, s));
+    if (!h.empty())
+        ARA_HIP(ctx, hipMemcpyAsync(sc + batch_pf_off(), h.data(), sizeof(BatchPf) * h.size(),
+                                    hipMemcpyHostToDevice, s));
+    const int32_t n_su = (int32_t)h.size();
     BatchArgs &B = plan->B;
     B.off = yet->d_off;
     B.ev = yet->d_ev;
@@ -899,11 +917,12 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     B.trial_begin = trial_major ? o.trial_begin : 0;
     B.trial_count = trial_major ? o.trial_count : 0;
     B.pfs = (const BatchPf *)(sc + batch_pf_off());
-    B.n_pf = n;
+    B.n_pf = n_su;
     B.tile = c.trial_tile;
     B.tail_band = o.tail_band;
     B.trial_major = trial_major ? 1 : 0;
-    B.n_items = trial_major ? ((o.trial_count + c.trial_tile - 1) / c.trial_tile) * (int64_t)n : items;
+    B.n_items = trial_major ? ((o.trial_count + c.trial_tile - 1) / c.trial_tile) * (int64_t)n_su
+                            : items;
     B.counter = (unsigned long long *)sc;
     B.redo_count = (uint32_t *)(sc + 8);
     B.redo = (unsigned long long *)(sc + batch_redo_off(n));
@@ -916,6 +935,20 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     plan->mode = o.sum_mode;
     plan->f64out = o.ylt_dtype == ARA_F64;
     return ARA_OK;
+}
+
+// The batched launch of a plan's secondary-uncertainty portfolios, then the
+// per-event table pass of each primary-uncertainty one, all on stream s.
+hipError_t launch_plan(const ara_context *ctx, const ara_yet *yet, const BatchPlan &plan,
+                       hipStream_t s) {
+    hipError_t e = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+    for (size_t k = 0; k < plan.pu.size() && e == hipSuccess; ++k) {
+        const PuItem &u = plan.pu[k];
+        if (u.count > 0)
+            e = enqueue_pu(ctx, yet, u.pf, u.begin, u.count, plan.mode, plan.f64out, u.ylt_layers,
+                           u.ylt_pf, nullptr, 0, plan.B.status, s);
+    }
+    return e;
 }
 
 ara_status prep_batch(ara_context *ctx, const ara_yet *yet, int32_t n, ara_portfolio *const *pfs,
@@ -946,7 +979,7 @@ ara_status ara_run_batch(ara_context *ctx, const ara_yet *yet, int32_t n_portfol
     ara_status st = prep_batch(ctx, yet, n_portfolios, pfs, opts, cfg, d_ylt_layers,
                                d_ylt_portfolio, d_scratch, scratch_bytes, s, &plan);
     if (st != ARA_OK) return st;
-    ARA_HIP(ctx, launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s));
+    ARA_HIP(ctx, launch_plan(ctx, yet, plan, s));
     return ARA_OK;
 }
 
@@ -979,12 +1012,12 @@ ara_status ara_batch_autotune(ara_context *ctx, const ara_yet *yet, int32_t n_po
                 if (st != ARA_OK) break;
                 hipError_t he = hipSuccess;
                 if (!warm) {
-                    he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+                    he = launch_plan(ctx, yet, plan, s);
                     warm = true;
                 }
                 if (he == hipSuccess) he = hipEventRecord(e0, s);
                 if (he == hipSuccess)
-                    he = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+                    he = launch_plan(ctx, yet, plan, s);
                 if (he == hipSuccess) he = hipEventRecord(e1, s);
                 if (he == hipSuccess) he = hipEventSynchronize(e1);
                 float ms = 0.0f;
@@ -1027,7 +1060,7 @@ ara_status ara_batch_graph_create(ara_context *ctx, const ara_yet *yet, int32_t 
         hipGraphExec_t x = nullptr;
         if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (he == hipSuccess) {
-            hipError_t le = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, cap);
+            hipError_t le = launch_plan(ctx, yet, plan, cap);
             he = hipStreamEndCapture(cap, &g);
             if (he == hipSuccess) he = le;
         }
@@ -1212,7 +1245,7 @@ ara_status run_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
     ara_status st = prep_batch_ranges(ctx, yet, n, pfs, opts, cfg, ylt_l, ylt_p, ranges, scratch,
                                       bytes, s, status, &plan);
     if (st != ARA_OK) return st;
-    ARA_HIP(ctx, launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s));
+    ARA_HIP(ctx, launch_plan(ctx, yet, plan, s));
     return ARA_OK;
 }
 size_t batch_scratch_need(int32_t n, int64_t total_trials) { return batch_need(n, total_trials); }

@@ -857,7 +857,9 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                     } else if (!REDO && (meta & (ROW_F64 | ROW_CORR))) {
                         // shapes outside the FP32 domain and the two-normal mix
                         // (whose special functions would inflate this pass's
-                        // register budget) are left to the second pass
+                        // register budget: inlined here they spill 387
+                        // registers at 7 waves per SIMD) are left to the
+                        // second pass
                         defer = true;
                     } else {
                         uint32_t jI, jC;
@@ -1450,7 +1452,7 @@ hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, cons
 // its compact record and in the per-row array.  keys[kShapeSlots] receives
 // the slots (0 = unused).
 __device__ __forceinline__ bool shape_eligible(const RowF &F) {
-    return !(F.meta & (ROW_DET | ROW_F64 | ROW_CORR));
+    return !(F.meta & (ROW_DET | ROW_F64));
 }
 __device__ __forceinline__ unsigned long long shape_key(const RowF &F) {
     return ((unsigned long long)__float_as_uint(F.a) << 32) | __float_as_uint(F.b);

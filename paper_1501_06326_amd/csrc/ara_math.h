@@ -397,9 +397,24 @@ __device__ inline double beta_quantile64(double a, double b, double lnb, double 
     const bool root_low = (z <= zc) ? (z <= Ih) : (zc >= Ihc);
     double A = a, B = b, Z = z, ZC = zc;
     if (!root_low) { A = b; B = a; Z = zc; ZC = z; }
-    // initial guess: the leading term of the small-x expansion
-    // I_x ~ x^A / (A B(A, B)), capped inside the bracket
-    double x = exp((log(Z) + log(A) + lnb) / A);
+    double x;
+    if (A >= 1.0 && B >= 1.0) {
+        // Abramowitz & Stegun 26.2.22 / 26.5.22 (as beta_guess32, in FP64):
+        // within a few per cent of the root for shapes of any size, where the
+        // small-x expansion below starts far off for large shapes
+        const bool lowz = Z < 0.5;
+        const double t = sqrt(-2.0 * log(lowz ? Z : ZC));
+        double y = t - (2.30753 + 0.27061 * t) / (1.0 + t * (0.99229 + 0.04481 * t));
+        if (!lowz) y = -y;
+        const double lam = (y * y - 3.0) / 6.0;
+        const double ra = 1.0 / (2.0 * A - 1.0), rb = 1.0 / (2.0 * B - 1.0);
+        const double rh = 0.5 * (ra + rb);
+        const double w = y * sqrt(1.0 / rh + lam) * rh - (rb - ra) * (lam + 5.0 / 6.0 - (2.0 / 3.0) * rh);
+        x = A / (A + B * exp(2.0 * w));
+    } else {
+        // the leading term of the small-x expansion I_x ~ x^A / (A B(A, B))
+        x = exp((log(Z) + log(A) + lnb) / A);
+    }
     if (!(x < 0.5)) x = 0.25;
     double y = beta_solve64(A, B, lnb, Z, ZC, x, 0.5, max_iter, ok);
     if (y == 0.0) *ok = true;    // root below the smallest double

@@ -1,11 +1,9 @@
 """Batched portfolios on the GPU: one persistent launch must reproduce, bit for
 bit, each secondary-uncertainty portfolio run alone (the draws are keyed by
 absolute trial, occurrence and elt_id, and a trial's arithmetic does not
-depend on its neighbours); a primary-uncertainty portfolio in a batch takes the
-per-occurrence path, whose trial sum is ordered differently from ara_run's
-gather-sum kernel, so it agrees to FP32 rounding (checked against the oracle
-with the per-trial tolerance).  Graph replays must reproduce the eager batch
-on every replay."""
+depend on its neighbours); a primary-uncertainty portfolio in a batch runs
+ara_run's per-event table pass after the launch, so it too equals ara_run bit
+for bit.  Graph replays must reproduce the eager batch on every replay."""
 import numpy as np
 import pytest
 
@@ -42,10 +40,6 @@ PU_INDEX = 2
 
 def same(outs, alone):
     for k, (o, r) in enumerate(zip(outs, alone)):
-        if k == PU_INDEX:
-            d = (o["ylt"] - r["ylt"]).abs().max().item()
-            assert d <= 1e-6 * r["ylt"].abs().max().item() + 1e-3
-            continue
         assert torch.equal(o["ylt"], r["ylt"])
         assert torch.equal(o["ylt_pf"], r["ylt_pf"])
 
@@ -75,8 +69,7 @@ def test_batch_trial_subrange(setup):
     for cfg in (None, (2, 16, 0), (2, 16, 1), (2, 0, 0), (1, 0, 1)):
         outs = a.run_batch(y, dps, trial_begin=1000, trial_count=2500, cfg=cfg)
         for k, (o, r) in enumerate(zip(outs, alone)):
-            if k != PU_INDEX:
-                assert torch.equal(o["ylt"], r["ylt"][:, 1000:3500])
+            assert torch.equal(o["ylt"], r["ylt"][:, 1000:3500])
 
 
 def test_batch_graph_replays(setup):
