@@ -566,8 +566,8 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
                                      p->d_row_cfrac, p->d_row_meta, p->d_row_lnb, p->d_otab,
                                      ctx->d_status, s));
         if (p->su_enabled)
-            ARA_HIP_P(launch_shape_collect(p->d_rowf, hl[l].row_base, liveoff_l, n_catalogue,
-                                           p->d_row_shape,
+            ARA_HIP_P(launch_shape_collect(p->d_rowf, hl[l].row_base, hl[l].n_rows, liveoff_l,
+                                           n_catalogue, p->d_row_shape,
                                            p->d_shape_keys + (size_t)l * kShapeSlots, s));
         if (!p->su_enabled)
             ARA_HIP_P(launch_build_sparse(p->d_otab + (size_t)l * n_catalogue, n_catalogue,

@@ -127,9 +127,9 @@ hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, cons
                                  int32_t *path, hipStream_t s);
 // shape tables: the distinct shapes of one layer's paying rows into keys
 // [kShapeSlots] (rows get their slot), then the tables of n_slots slots
-hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, const uint32_t *liveoff,
-                                int32_t n_cat, uint32_t *row_shape, unsigned long long *keys,
-                                hipStream_t s);
+hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, int64_t n_rows,
+                                const uint32_t *liveoff, int32_t n_cat, uint32_t *row_shape,
+                                unsigned long long *keys, hipStream_t s);
 hipError_t launch_shape_tables(const unsigned long long *keys, int64_t n_slots, float *tab,
                                hipStream_t s);
 

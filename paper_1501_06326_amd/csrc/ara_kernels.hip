@@ -1444,13 +1444,16 @@ hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, cons
 // shape tables
 // ---------------------------------------------------------------------------
 // The distinct Beta shapes of one layer's paying rows on the FP32 quantile
-// path into kShapeSlots slots, one block per layer, by a rule that depends on
-// the rows alone (so every load of a portfolio gives every row the same
-// path): each thread lists the first distinct shapes of its contiguous
-// chunk of rows in row order, thread 0 merges the lists in chunk order until
-// the slots are full, and every paying row then gets 1 + its slot, or 0, in
-// its compact record and in the per-row array.  keys[kShapeSlots] receives
-// the slots (0 = unused).
+// path into kShapeSlots slots, by a rule that depends on the rows alone (so
+// every load of a portfolio gives every row the same path): among the
+// layer's first kShapeScan paying rows, each thread lists the first distinct
+// shapes of its contiguous chunk in row order and thread 0 merges the lists
+// in chunk order until the slots are full (one block per layer; keys
+// [kShapeSlots] receives the slots, 0 = unused).  k_shape_assign then gives
+// every paying row 1 + its slot, or 0, in its compact record and in the
+// per-row array.
+constexpr uint32_t kShapeScan = 4096;
+
 __device__ __forceinline__ bool shape_eligible(const RowF &F) {
     return !(F.meta & (ROW_DET | ROW_F64));
 }
@@ -1458,16 +1461,16 @@ __device__ __forceinline__ unsigned long long shape_key(const RowF &F) {
     return ((unsigned long long)__float_as_uint(F.a) << 32) | __float_as_uint(F.b);
 }
 
-__global__ __launch_bounds__(256) void k_shape_collect(RowF *__restrict__ rowf, int64_t row_base,
+__global__ __launch_bounds__(256) void k_shape_collect(const RowF *__restrict__ rowf,
+                                                       int64_t row_base,
                                                        const uint32_t *__restrict__ liveoff,
                                                        int32_t n_cat,
-                                                       uint32_t *__restrict__ row_shape,
                                                        unsigned long long *__restrict__ keys) {
     __shared__ unsigned long long loc[256][kShapeSlots];
     __shared__ int locn[256];
     __shared__ unsigned long long slot[kShapeSlots];
     const int tid = threadIdx.x;
-    const uint32_t n = liveoff[n_cat];
+    const uint32_t n = min(liveoff[n_cat], kShapeScan);
     const uint32_t per = (n + 255u) / 256u;
     const uint32_t lo = (uint32_t)tid * per, hi = min(n, lo + per);
     int m = 0;
@@ -1493,7 +1496,19 @@ __global__ __launch_bounds__(256) void k_shape_collect(RowF *__restrict__ rowf, 
         for (int k = ns; k < kShapeSlots; ++k) slot[k] = 0ull;
     }
     __syncthreads();
-    for (uint32_t i = (uint32_t)tid; i < n; i += 256u) {
+    if (tid < kShapeSlots) keys[tid] = slot[tid];
+}
+
+__global__ __launch_bounds__(256) void k_shape_assign(RowF *__restrict__ rowf, int64_t row_base,
+                                                      const uint32_t *__restrict__ liveoff,
+                                                      int32_t n_cat,
+                                                      const unsigned long long *__restrict__ keys,
+                                                      uint32_t *__restrict__ row_shape) {
+    __shared__ unsigned long long slot[kShapeSlots];
+    if (threadIdx.x < kShapeSlots) slot[threadIdx.x] = keys[threadIdx.x];
+    __syncthreads();
+    const uint32_t n = liveoff[n_cat];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         RowF &F = rowf[row_base + i];
         uint32_t sh = 0;
         if (shape_eligible(F)) {
@@ -1507,7 +1522,6 @@ __global__ __launch_bounds__(256) void k_shape_collect(RowF *__restrict__ rowf, 
         F.shape = sh;
         row_shape[row_base + F.row] = sh;
     }
-    if (tid < kShapeSlots) keys[tid] = slot[tid];
 }
 
 // The tables of the used slots: one block per slot, one thread per point.
@@ -1522,11 +1536,14 @@ __global__ __launch_bounds__(2 * kShapeK) void k_shape_tables(const unsigned lon
     tab[(size_t)blockIdx.x * 2 * kShapeK + threadIdx.x] = shape_table_logit(a, b, lnb, upper, k);
 }
 
-hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, const uint32_t *liveoff,
-                                int32_t n_cat, uint32_t *row_shape, unsigned long long *keys,
-                                hipStream_t s) {
+hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, int64_t n_rows,
+                                const uint32_t *liveoff, int32_t n_cat, uint32_t *row_shape,
+                                unsigned long long *keys, hipStream_t s) {
     hipLaunchKernelGGL(k_shape_collect, dim3(1), dim3(256), 0, s, rowf, row_base, liveoff, n_cat,
-                       row_shape, keys);
+                       keys);
+    // a grid over the layer's rows (the paying ones are a prefix of them)
+    hipLaunchKernelGGL(k_shape_assign, dim3(grid_for(n_rows > 0 ? n_rows : 1, 256, 1024)),
+                       dim3(256), 0, s, rowf, row_base, liveoff, n_cat, keys, row_shape);
     return hipGetLastError();
 }
 
