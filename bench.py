@@ -140,7 +140,7 @@ def main():
                     help="also run one elementwise kernel that reads and writes 1 GiB (a "
                          "known-size kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--mode", choices=["step", "batched", "served", "precision", "views",
-                                       "probes", "variants"], default="step")
+                                       "probes", "variants", "footprint"], default="step")
     ap.add_argument("--oracle-trials", type=int, default=3000, help="precision mode")
     ap.add_argument("--portfolios", type=int, default=64, help="batched mode")
     ap.add_argument("--graph", action="store_true", help="batched mode: also time a graph replay")
@@ -168,6 +168,8 @@ def main():
         return bench_probes(args)
     if args.mode == "variants":
         return bench_variants(args)
+    if args.mode == "footprint":
+        return bench_footprint(args)
 
     import torch
     from paper_1501_06326_amd import Ara, evaluations
@@ -500,6 +502,64 @@ def bench_variants(args):
                       "data": "synthetic (seeded numpy generator; lognormal ELT means)",
                       "config": {"workload": w.name, "trials": n, "occurrences": yet.n_occ,
                                  "elts": 16, "sum_mode": "kahan32"}, **res}), flush=True)
+    ara.close()
+
+
+def bench_footprint(args):
+    """The lean secondary-uncertainty pass at a fixed number of hits per
+    occurrence while the paying-row table grows: catalogues of 12,500 to
+    200,000 events, 16 ELTs of catalogue / 5 rows each (the full shape's
+    density), Poisson(1000) occurrences, --trials trials (default 300,000 in
+    this mode).  The row records and (first row, count) pairs the pass
+    gathers grow with the catalogue, so the time per occurrence shows what
+    those gathers' cache misses cost."""
+    import torch
+    from paper_1501_06326_amd import Ara
+    from workloads import (SEED_ELT_BASE, SEED_PHILOX, SEED_YET_FULL, Layer, Portfolio, make_elt,
+                           make_yet)
+
+    trials = args.trials if args.trials != 1_000_000 else 300_000
+    ara = Ara(0)
+    dev = ara.device
+    stream = torch.cuda.current_stream()
+    rows_out = []
+    for cat in (12_500, 25_000, 50_000, 100_000, 200_000):
+        yet = make_yet(trials, 1000.0, cat, SEED_YET_FULL, with_times=False)
+        elts = [make_elt(e, cat // 5, cat, SEED_ELT_BASE + e, retention=1e6, limit=5e7)
+                for e in range(16)]
+        pf = Portfolio(layers=[Layer(elts=elts, occ_retention=1e7, occ_limit=2e8,
+                                     agg_retention=5e7, agg_limit=1e9)],
+                       seed=SEED_PHILOX, su_enabled=True)
+        off = torch.from_numpy(yet.offsets).to(dev)
+        ev = torch.from_numpy(yet.event_ids).to(dev)
+        y = ara.load_yet(yet, device_arrays=(off, ev, None))
+        p = ara.load_portfolio(pf, cat)
+        n = yet.n_trials
+        out_p = torch.empty(n, dtype=torch.float32, device=dev)
+        scratch = torch.empty(ara.run_scratch_size(n), dtype=torch.uint8, device=dev)
+        ara.run(y, p, out_pf=out_p, layers=False, scratch=scratch)      # warmup, status check
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ara.run(y, p, out_pf=out_p, layers=False, scratch=scratch, sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ara.sync_status()
+        ms = e0.elapsed_time(e1) / args.steps
+        hits = ara.run(y, p, diagnostics=True, out_pf=out_p)["hits"].sum().item()
+        row = {"catalogue": cat, "rows_per_elt": cat // 5, "occurrences": yet.n_occ,
+               "ms_per_run": ms, "ns_per_occurrence": 1e6 * ms / yet.n_occ,
+               "nonzero_lookups_per_occurrence": hits / yet.n_occ}
+        rows_out.append(row)
+        log(f"catalogue {cat}: {ms:.3f} ms, {row['ns_per_occurrence']:.4f} ns per occurrence")
+        ara.free_portfolio(p)
+        del p, y, off, ev, out_p, scratch
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "lean secondary-uncertainty pass time vs paying-row footprint",
+                      "n_gpus": 1, "steps": args.steps, "trials": trials,
+                      "data": "synthetic (seeded numpy generator; lognormal ELT means)",
+                      "runs": rows_out}), flush=True)
     ara.close()
 
 
