@@ -684,6 +684,7 @@ ara_status run_impl(ara_context *ctx, const ara_yet *yet, const ara_portfolio *p
     p.occ_view = o.d_occ_view;
     p.occ_stride = o.occ_view_stride;
     p.status = ctx->d_status;
+    p.redo_w4 = (pf->all_flags & ROW_F64) && !(pf->all_flags & ROW_CORR);
     const size_t need = run_scratch_need(o.trial_count);
     char *scr = (char *)o.d_scratch;
     if (static_scratch) {

@@ -53,6 +53,7 @@ struct SuLaunch {
     int32_t *redo;            // [trial_count] scratch: trials handed to the FP64-capable pass
     uint32_t *redo_count;     // scratch counter
     int redo_grid;            // blocks of the second pass
+    int redo_w4;              // second pass at 4 wavefronts per SIMD (FP64-quantile rows, no mix)
     int32_t f64_iters;        // step limit of the FP64 quantile
     const float *shape_tab;   // shape tables [layer][kShapeSlots][2][kShapeK]
     const uint32_t *row_shape;   // per row: 1 + shape slot, or 0

@@ -1021,11 +1021,9 @@ __global__ __launch_bounds__(64) ARA_SU_OCCUPANCY void k_ara_su(SuArgs A, Philox
 
 // FP64-capable pass over the trials the main pass handed over; the count is
 // read on the device, so no host round trip is needed between the passes.
-template <int MODE, bool F64OUT, bool DIAG, bool OCC = false>
-__global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
-    __shared__ float X[kSeg];
-    __shared__ uint2 Q[kQCap];
-    __shared__ EltDev El[kEltLds];
+template <int MODE, bool F64OUT, bool DIAG, bool OCC>
+__device__ __forceinline__ void su_redo_loop(const SuArgs &A, const PhiloxKeys &keys, float *X,
+                                             uint2 *Q, EltDev *El) {
     // the list holds at most one entry per trial of the run; an entry outside
     // the run (scratch shared by runs that overlapped, against the contract)
     // is reported instead of followed
@@ -1039,6 +1037,29 @@ __global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
         }
         su_trial<MODE, F64OUT, DIAG, true, OCC>(A, keys, (int64_t)t, X, Q, El);
     }
+}
+
+template <int MODE, bool F64OUT, bool DIAG, bool OCC = false>
+__global__ __launch_bounds__(64) void k_ara_su_redo(SuArgs A, PhiloxKeys keys) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
+    su_redo_loop<MODE, F64OUT, DIAG, OCC>(A, keys, X, Q, El);
+}
+
+// The same pass held to 4 wavefronts per SIMD (128 registers, spilling the
+// rest): for portfolios whose handed-over draws are FP64 quantiles (shapes
+// outside the FP32 domain, capped sigma) four resident wavefronts hide more
+// of the FP64 latency than one unspilled one; with two-normal-mix rows the
+// FP32 special functions of the mix spill too and the one-wavefront form
+// above is faster (both measured on the full shape).
+template <int MODE, bool F64OUT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_ara_su_redo4(
+    SuArgs A, PhiloxKeys keys) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
+    su_redo_loop<MODE, F64OUT, false, false>(A, keys, X, Q, El);
 }
 
 // ---------------------------------------------------------------------------
@@ -1374,7 +1395,10 @@ static hipError_t su_dispatch2(const SuLaunch &p, hipStream_t s) {
         hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, false, true>), gr, dim3(64), 0, s, A, keys);
     } else {
         hipLaunchKernelGGL((k_ara_su<MODE, F64OUT, false>), g, dim3(64), 0, s, A, keys);
-        hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, false>), gr, dim3(64), 0, s, A, keys);
+        if (p.redo_w4)
+            hipLaunchKernelGGL((k_ara_su_redo4<MODE, F64OUT>), gr, dim3(64), 0, s, A, keys);
+        else
+            hipLaunchKernelGGL((k_ara_su_redo<MODE, F64OUT, false>), gr, dim3(64), 0, s, A, keys);
     }
     return hipGetLastError();
 }

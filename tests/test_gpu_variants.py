@@ -92,9 +92,19 @@ def test_paper_keying_in_a_batch(ara):
 
 @pytest.mark.parametrize("corr", [False, True])
 def test_sigma_capped_rows(ara, corr):
+    """Rows above the sigma cap take the FP64 quantile in the second pass
+    (without mixed rows its 4-wavefront form, the diagnostic pass its
+    1-wavefront form): parity with the oracle, and the fast pass gives the
+    diagnostic pass's YLT bit for bit."""
     w = config_small(corr=corr, n_trials=2000)
     say("sigma capped rows", corr)
-    parity(ara, w.yet, sigma_capped(w.portfolio))
+    pf = sigma_capped(w.portfolio)
+    r, ref = parity(ara, w.yet, pf)
+    y = ara.load_yet(w.yet)
+    p = ara.load_portfolio(pf, w.yet.n_catalogue)
+    assert torch.equal(ara.run(y, p)["ylt"], r["ylt"])
+    ara.free_portfolio(p)
+    ara.free_yet(y)
 
 
 @pytest.mark.parametrize("corr", [False, True])
