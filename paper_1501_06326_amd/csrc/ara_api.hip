@@ -823,6 +823,7 @@ struct BatchPlan {
     BatchArgs B;
     int grid, redo_grid, mode;
     bool f64out;
+    bool redo_w4;       // second pass at 4 wavefronts per SIMD (see k_ara_su_redo4)
     std::vector<PuItem> pu;
 };
 
@@ -862,6 +863,7 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
         return fail(ctx, ARA_E_INVALID_ARG, "ara_run_batch: trial-major order needs one trial range");
     int64_t total = 0, items = 0;
     std::vector<BatchPf> h;
+    uint32_t su_flags = 0;     // OR of the row flags of the batch's SU portfolios
     h.reserve((size_t)n);
     plan->pu.clear();
     for (int32_t i = 0; i < n; ++i) {
@@ -879,6 +881,7 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
             plan->pu.push_back({p, tb, tc, ylt_l ? ylt_l[i] : nullptr, ylt_p ? ylt_p[i] : nullptr});
             continue;
         }
+        su_flags |= p->all_flags;
         h.emplace_back();
         BatchPf &b = h.back();
         b.layers = p->d_layers;
@@ -932,7 +935,8 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
         return fail(ctx, ARA_E_UNSUPPORTED, "ara_run_batch: more than 2^31 work items for the "
                                             "one-workgroup-per-item form; use waves_per_cu > 0");
     plan->grid = ctx->n_cu * c.waves_per_cu;           // 0: one workgroup per item
-    plan->redo_grid = ctx->n_cu * 4;
+    plan->redo_w4 = (su_flags & ROW_F64) && !(su_flags & ROW_CORR);
+    plan->redo_grid = ctx->n_cu * 4 * (plan->redo_w4 ? 4 : 1);
     plan->mode = o.sum_mode;
     plan->f64out = o.ylt_dtype == ARA_F64;
     return ARA_OK;
@@ -942,7 +946,7 @@ ara_status prep_batch_ranges(ara_context *ctx, const ara_yet *yet, int32_t n,
 // per-event table pass of each primary-uncertainty one, all on stream s.
 hipError_t launch_plan(const ara_context *ctx, const ara_yet *yet, const BatchPlan &plan,
                        hipStream_t s) {
-    hipError_t e = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, s);
+    hipError_t e = launch_batch(plan.B, plan.mode, plan.f64out, plan.grid, plan.redo_grid, plan.redo_w4, s);
     for (size_t k = 0; k < plan.pu.size() && e == hipSuccess; ++k) {
         const PuItem &u = plan.pu[k];
         if (u.count > 0)

@@ -117,6 +117,7 @@ hipError_t launch_build_sparse(const float *otab, int32_t n_cat, uint32_t *bits,
                                float *vals, LayerDev *d_layer, hipStream_t s);
 hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s);
 hipError_t launch_batch(const BatchArgs &B, int mode, bool f64out, int grid, int redo_grid,
+                        bool redo_w4,
                         hipStream_t s);
 // exclusive prefix sum of p[0, n) in place (one block; also used by the
 // exceedance-curve sort for its digit counts)

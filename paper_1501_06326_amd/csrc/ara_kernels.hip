@@ -1178,10 +1178,7 @@ __global__ __launch_bounds__(64) ARA_SU_OCCUPANCY void k_ara_batch_items(BatchAr
 }
 
 template <int MODE, bool F64OUT>
-__global__ __launch_bounds__(64) void k_ara_batch_redo(BatchArgs B) {
-    __shared__ float X[kSeg];
-    __shared__ uint2 Q[kQCap];
-    __shared__ EltDev El[kEltLds];
+__device__ __forceinline__ void batch_redo_loop(const BatchArgs &B, float *X, uint2 *Q, EltDev *El) {
     const uint32_t n = *B.redo_count;
     for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
         const unsigned long long e = B.redo[r];
@@ -1196,6 +1193,24 @@ __global__ __launch_bounds__(64) void k_ara_batch_redo(BatchArgs B) {
         batch_view(B, p, A, keys);
         su_trial<MODE, F64OUT, false, true>(A, keys, t, X, Q, El);
     }
+}
+
+template <int MODE, bool F64OUT>
+__global__ __launch_bounds__(64) void k_ara_batch_redo(BatchArgs B) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
+    batch_redo_loop<MODE, F64OUT>(B, X, Q, El);
+}
+
+// the batch's second pass in the register budget of k_ara_su_redo4
+template <int MODE, bool F64OUT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_ara_batch_redo4(
+    BatchArgs B) {
+    __shared__ float X[kSeg];
+    __shared__ uint2 Q[kQCap];
+    __shared__ EltDev El[kEltLds];
+    batch_redo_loop<MODE, F64OUT>(B, X, Q, El);
 }
 
 // ---------------------------------------------------------------------------
@@ -1421,28 +1436,32 @@ hipError_t launch_su(const SuLaunch &p, int mode, bool f64out, hipStream_t s) {
 // grid <= 0: one workgroup per work item; otherwise the persistent form with
 // that many workgroups.
 template <int MODE, bool F64OUT>
-static void batch_dispatch(const BatchArgs &B, int grid, int redo_grid, hipStream_t s) {
+static void batch_dispatch(const BatchArgs &B, int grid, int redo_grid, bool redo_w4,
+                           hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B.counter, B.redo_count);
     if (grid <= 0)
         hipLaunchKernelGGL((k_ara_batch_items<MODE, F64OUT>), dim3((unsigned)B.n_items), dim3(64),
                            0, s, B);
     else
         hipLaunchKernelGGL((k_ara_batch<MODE, F64OUT>), dim3(grid), dim3(64), 0, s, B);
-    hipLaunchKernelGGL((k_ara_batch_redo<MODE, F64OUT>), dim3(redo_grid), dim3(64), 0, s, B);
+    if (redo_w4)
+        hipLaunchKernelGGL((k_ara_batch_redo4<MODE, F64OUT>), dim3(redo_grid), dim3(64), 0, s, B);
+    else
+        hipLaunchKernelGGL((k_ara_batch_redo<MODE, F64OUT>), dim3(redo_grid), dim3(64), 0, s, B);
 }
 
 hipError_t launch_batch(const BatchArgs &B, int mode, bool f64out, int grid, int redo_grid,
-                        hipStream_t s) {
+                        bool redo_w4, hipStream_t s) {
     if (B.n_items <= 0 || B.n_pf <= 0) return hipSuccess;
     if (mode == ARA_SUM_NAIVE32) {
-        if (f64out) batch_dispatch<ARA_SUM_NAIVE32, true>(B, grid, redo_grid, s);
-        else batch_dispatch<ARA_SUM_NAIVE32, false>(B, grid, redo_grid, s);
+        if (f64out) batch_dispatch<ARA_SUM_NAIVE32, true>(B, grid, redo_grid, redo_w4, s);
+        else batch_dispatch<ARA_SUM_NAIVE32, false>(B, grid, redo_grid, redo_w4, s);
     } else if (mode == ARA_SUM_KAHAN32) {
-        if (f64out) batch_dispatch<ARA_SUM_KAHAN32, true>(B, grid, redo_grid, s);
-        else batch_dispatch<ARA_SUM_KAHAN32, false>(B, grid, redo_grid, s);
+        if (f64out) batch_dispatch<ARA_SUM_KAHAN32, true>(B, grid, redo_grid, redo_w4, s);
+        else batch_dispatch<ARA_SUM_KAHAN32, false>(B, grid, redo_grid, redo_w4, s);
     } else {
-        if (f64out) batch_dispatch<ARA_SUM_F64, true>(B, grid, redo_grid, s);
-        else batch_dispatch<ARA_SUM_F64, false>(B, grid, redo_grid, s);
+        if (f64out) batch_dispatch<ARA_SUM_F64, true>(B, grid, redo_grid, redo_w4, s);
+        else batch_dispatch<ARA_SUM_F64, false>(B, grid, redo_grid, redo_w4, s);
     }
     return hipGetLastError();
 }
