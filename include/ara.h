@@ -188,7 +188,10 @@ ara_status ara_free_yet(ara_context *ctx, ara_yet *yet);
  * builds there, with device kernels, each layer's event-indexed direct-access
  * structure and the per-row Beta fit; it synchronises the stream.  The
  * workspace belongs to the portfolio until ara_free_portfolio; the host
- * arrays of the description may be freed on return. */
+ * arrays of the description may be freed on return.  Both return
+ * ARA_E_UNSUPPORTED for a layer of 2^27 or more ELT rows (the compact row
+ * records hold a layer-local row index in 27 bits) or a portfolio of 2^32 or
+ * more. */
 ara_status ara_portfolio_workspace_size(const ara_portfolio_desc *desc, int32_t n_catalogue,
                                         size_t *bytes);
 ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,

@@ -128,6 +128,7 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
             !(ld.agg_limit >= 0) || std::isinf(ld.occ_retention) || std::isinf(ld.agg_retention))
             return fail(ctx, ARA_E_BAD_ELT_ROW, "layer %d: terms must be finite retentions >= 0 "
                                                 "and limits >= 0", l);
+        int64_t layer_rows = 0;
         for (int j = 0; j < ld.n_elts; ++j) {
             const ara_elt_desc &e = ld.elts[j];
             if (e.n_rows < 0 || (e.n_rows > 0 && (!e.event_ids || !e.mean)))
@@ -137,7 +138,10 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
                 return fail(ctx, ARA_E_BAD_ELT_ROW, "layer %d ELT %d: share must be in [0,1], "
                                                     "retention finite >= 0, limit >= 0", l, j);
             rows += e.n_rows;
+            layer_rows += e.n_rows;
         }
+        if (layer_rows >= kRowFMaxRows)
+            return fail(ctx, ARA_E_UNSUPPORTED, "layer %d: 2^27 or more ELT rows in one layer", l);
         ne += ld.n_elts;
         if (ld.n_elts > mx) mx = ld.n_elts;
     }
@@ -166,7 +170,7 @@ ara_status plan(ara_context *ctx, const ara_portfolio_desc *d, int32_t n_cat, La
     L->row_shape = o; o += su ? align256(sizeof(uint32_t) * (size_t)(rows ? rows : 1)) : 0;
     L->shape_keys = o; o += su ? align256(sizeof(unsigned long long) * kShapeSlots * (nl ? nl : 1)) : 0;
     L->shape_tab = o;
-    o += su ? align256(sizeof(float) * 2 * kShapeK * kShapeSlots * (size_t)(nl ? nl : 1)) : 0;
+    o += su ? align256(sizeof(float) * kShapeStride * kShapeSlots * (size_t)(nl ? nl : 1)) : 0;
     const size_t nw = ((size_t)n_cat + 31) / 32;
     const bool pu = !d->su_enabled;
     L->otab = o; o += pu ? align256(sizeof(float) * (size_t)nl * n_cat) : 0;
@@ -267,7 +271,7 @@ uint32_t fbits(float v) {
 ara_status one_shape_table(ara_context *ctx, float a, float b, hipStream_t s, void **mem,
                            float **tab) {
     *mem = nullptr;
-    const size_t bytes = 256 + sizeof(float) * 2 * kShapeK;
+    const size_t bytes = 256 + sizeof(float) * kShapeStride;
     ARA_HIP(ctx, hipMalloc(mem, bytes));
     const unsigned long long key = ((unsigned long long)fbits(a) << 32) | fbits(b);
     ARA_HIP(ctx, hipMemcpyAsync(*mem, &key, sizeof key, hipMemcpyHostToDevice, s));
@@ -566,7 +570,7 @@ ara_status ara_load_portfolio(ara_context *ctx, const ara_portfolio_desc *desc,
                                      p->d_row_cfrac, p->d_row_meta, p->d_row_lnb, p->d_otab,
                                      ctx->d_status, s));
         if (p->su_enabled)
-            ARA_HIP_P(launch_shape_collect(p->d_rowf, hl[l].row_base, hl[l].n_rows, liveoff_l,
+            ARA_HIP_P(launch_shape_collect(p->d_rowf, p->d_rowq, hl[l].row_base, hl[l].n_rows, liveoff_l,
                                            n_catalogue, p->d_row_shape,
                                            p->d_shape_keys + (size_t)l * kShapeSlots, s));
         if (!p->su_enabled)

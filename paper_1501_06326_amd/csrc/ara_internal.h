@@ -54,17 +54,23 @@ struct RowQ {
 };
 
 // Compact record of a row that can pay, read by the fast passes with one
-// 32-byte load (one cache line): the layer's such rows are contiguous,
-// event-major.  row is the index of the same row in the per-row arrays;
-// shape is 1 + the slot of the row's Beta shape among the layer's shape
-// tables, or 0 when the row has none.
+// 16-byte load: the layer's such rows are contiguous, event-major.  rs packs
+// the index of the same row in the layer's per-row arrays (bits 5-31, so a
+// layer holds fewer than kRowFMaxRows rows) and 1 + the slot of the row's
+// Beta shape among the layer's shape tables, or 0 when it has none (bits
+// 0-4); cfrac is the two-normal mix weight.  A row with a slot takes its
+// Beta parameters (alpha, beta, log2 B(alpha, beta)) from the slot, which
+// holds exactly the values of its rows (they are functions of the shape
+// alone); a row without one reads them from the per-row arrays.
 struct __attribute__((aligned(16))) RowF {
-    float scale, a, b, lnb;
+    float scale;
     uint32_t meta;
+    uint32_t rs;
     float cfrac;
-    uint32_t row;
-    uint32_t shape;
 };
+constexpr int64_t kRowFMaxRows = (int64_t)1 << 27;
+__host__ __device__ inline uint32_t rowf_row(const RowF &F) { return F.rs >> 5; }
+__host__ __device__ inline uint32_t rowf_shape(const RowF &F) { return F.rs & 31u; }
 
 // Raw host rows staged on the device for the build kernels.
 struct RawRow {
@@ -108,6 +114,8 @@ constexpr int kF64QuantileIters = 400;
 // shape of the FP32 domain, close enough for a single Halley step.
 constexpr int kShapeSlots = 16;
 constexpr int kShapeK = 128;
+// floats per slot: the two halves, then (alpha, beta, log2 B(alpha, beta), 0)
+constexpr int kShapeStride = 2 * kShapeK + 4;
 constexpr double kShapeTLo = 1.1774100225154747;   // sqrt(2 ln 2)
 constexpr double kShapeTHi = 5.768107546403532;    // sqrt(48 ln 2)
 
@@ -146,7 +154,7 @@ struct ara_portfolio {
     double *d_row_lnb;
     uint32_t *d_row_shape;     // per row: 1 + its shape slot, or 0
     unsigned long long *d_shape_keys;   // [layer][kShapeSlots]: (alpha, beta) bits, 0 = unused
-    float *d_shape_tab;        // [layer][kShapeSlots][2][kShapeK]
+    float *d_shape_tab;        // [layer][kShapeSlots][kShapeStride]
     float *d_otab;
     uint32_t *d_sp_bits;       // per layer [nw]: bitmap of the non-zero otab entries
     uint32_t *d_sp_rank;       // per layer [nw + 1]: set bits before each word

@@ -55,7 +55,7 @@ struct SuLaunch {
     int redo_grid;            // blocks of the second pass
     int redo_w4;              // second pass at 4 wavefronts per SIMD (FP64-quantile rows, no mix)
     int32_t f64_iters;        // step limit of the FP64 quantile
-    const float *shape_tab;   // shape tables [layer][kShapeSlots][2][kShapeK]
+    const float *shape_tab;   // shape tables [layer][kShapeSlots][kShapeStride]
     const uint32_t *row_shape;   // per row: 1 + shape slot, or 0
     void *occ_view;           // optional occurrence view (see ara_run_opts)
     int64_t occ_stride;
@@ -72,7 +72,7 @@ struct BatchPf {
     const float *row_cfrac;
     const uint32_t *row_meta;
     const double *row_lnb;
-    const float *shape_tab;    // shape tables [layer][kShapeSlots][2][kShapeK]
+    const float *shape_tab;    // shape tables [layer][kShapeSlots][kShapeStride]
     void *ylt_layers;
     void *ylt_pf;
     uint32_t k0, k1;           // Philox key (the portfolio's seed)
@@ -129,7 +129,7 @@ hipError_t launch_debug_quantile(int64_t n, const float *a, const float *b, cons
                                  int32_t *path, hipStream_t s);
 // shape tables: the distinct shapes of one layer's paying rows into keys
 // [kShapeSlots] (rows get their slot), then the tables of n_slots slots
-hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, int64_t n_rows,
+hipError_t launch_shape_collect(RowF *rowf, const RowQ *rowq, int64_t row_base, int64_t n_rows,
                                 const uint32_t *liveoff, int32_t n_cat, uint32_t *row_shape,
                                 unsigned long long *keys, hipStream_t s);
 hipError_t launch_shape_tables(const unsigned long long *keys, int64_t n_slots, float *tab,

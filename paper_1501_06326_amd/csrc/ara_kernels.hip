@@ -396,13 +396,9 @@ __global__ void k_ev_fill(const int32_t *__restrict__ dat, const RawRow *__restr
                 if (!dead) {
                     RowF F;
                     F.scale = q.scale;
-                    F.a = q.a;
-                    F.b = q.b;
-                    F.lnb = q.lnb;
                     F.meta = f | (uint32_t)j;
+                    F.rs = (uint32_t)(pos - L.row_base) << 5;   // shape set by k_shape_assign
                     F.cfrac = cf;
-                    F.row = (uint32_t)(pos - L.row_base);
-                    F.shape = 0u;          // set by k_shape_collect
                     rowf[fpos++] = F;
                 }
                 ++pos;
@@ -713,7 +709,7 @@ struct SuArgs {
     int32_t *redo;            // trials (relative index) handed to the FP64-capable pass
     uint32_t *redo_count;
     int32_t f64_iters;        // step limit of the FP64 quantile
-    const float *shape_tab;   // the portfolio's shape tables ([layer][kShapeSlots][2][kShapeK])
+    const float *shape_tab;   // the portfolio's shape tables ([layer][kShapeSlots][kShapeStride])
     const uint32_t *row_shape;   // per row: 1 + its shape slot, or 0 (the diagnostic pass)
     void *occ_view;           // occurrence view, written by the DIAG and OCC instantiations
     int64_t occ_stride;
@@ -824,17 +820,31 @@ __device__ __forceinline__ bool su_trial(const SuArgs &A, const PhiloxKeys &keys
                         const RowF F = A.rowf[row];
                         meta = F.meta;
                         q.scale = F.scale;
-                        q.a = F.a;
-                        q.b = F.b;
-                        q.lnb = F.lnb;
+                        orow = (uint32_t)rb0 + rowf_row(F);
+                        shape = rowf_shape(F);
                         cfrac = F.cfrac;
-                        orow = (uint32_t)rb0 + F.row;
-                        shape = F.shape;
                     }
                     // the row's shape table, when its shape has a slot
                     const float *tab =
-                        shape ? A.shape_tab + ((size_t)l * kShapeSlots + (shape - 1u)) * 2 * kShapeK
+                        shape ? A.shape_tab + ((size_t)l * kShapeSlots + (shape - 1u)) * kShapeStride
                               : nullptr;
+                    if (!DIAG) {
+                        // Beta parameters: the slot's (the lanes of a batch mostly share
+                        // one), else the row's own
+                        if (tab) {
+                            const float4 h = *reinterpret_cast<const float4 *>(tab + 2 * kShapeK);
+                            q.a = h.x;
+                            q.b = h.y;
+                            q.lnb = h.z;
+                        } else if (!(meta & ROW_DET)) {
+                            const RowQ r = A.rowq[orow];
+                            q.a = r.a;
+                            q.b = r.b;
+                            q.lnb = r.lnb;
+                        } else {
+                            q.a = q.b = q.lnb = 0.0f;
+                        }
+                    }
                     const uint32_t ei = meta & 0xffffu;
                     // the layer's ELT record: an LDS read when the layer's records
                     // are staged (the global read is a different instruction, so the
@@ -1500,11 +1510,12 @@ constexpr uint32_t kShapeScan = 4096;
 __device__ __forceinline__ bool shape_eligible(const RowF &F) {
     return !(F.meta & (ROW_DET | ROW_F64));
 }
-__device__ __forceinline__ unsigned long long shape_key(const RowF &F) {
-    return ((unsigned long long)__float_as_uint(F.a) << 32) | __float_as_uint(F.b);
+__device__ __forceinline__ unsigned long long shape_key(const RowQ &q) {
+    return ((unsigned long long)__float_as_uint(q.a) << 32) | __float_as_uint(q.b);
 }
 
 __global__ __launch_bounds__(256) void k_shape_collect(const RowF *__restrict__ rowf,
+                                                       const RowQ *__restrict__ rowq,
                                                        int64_t row_base,
                                                        const uint32_t *__restrict__ liveoff,
                                                        int32_t n_cat,
@@ -1520,7 +1531,7 @@ __global__ __launch_bounds__(256) void k_shape_collect(const RowF *__restrict__ 
     for (uint32_t i = lo; i < hi && m < kShapeSlots; ++i) {
         const RowF F = rowf[row_base + i];
         if (!shape_eligible(F)) continue;
-        const unsigned long long key = shape_key(F);
+        const unsigned long long key = shape_key(rowq[row_base + rowf_row(F)]);
         bool seen = false;
         for (int q = 0; q < m; ++q) seen = seen || loc[tid][q] == key;
         if (!seen) loc[tid][m++] = key;
@@ -1542,7 +1553,8 @@ __global__ __launch_bounds__(256) void k_shape_collect(const RowF *__restrict__ 
     if (tid < kShapeSlots) keys[tid] = slot[tid];
 }
 
-__global__ __launch_bounds__(256) void k_shape_assign(RowF *__restrict__ rowf, int64_t row_base,
+__global__ __launch_bounds__(256) void k_shape_assign(RowF *__restrict__ rowf,
+                                                      const RowQ *__restrict__ rowq, int64_t row_base,
                                                       const uint32_t *__restrict__ liveoff,
                                                       int32_t n_cat,
                                                       const unsigned long long *__restrict__ keys,
@@ -1555,15 +1567,15 @@ __global__ __launch_bounds__(256) void k_shape_assign(RowF *__restrict__ rowf, i
         RowF &F = rowf[row_base + i];
         uint32_t sh = 0;
         if (shape_eligible(F)) {
-            const unsigned long long key = shape_key(F);
+            const unsigned long long key = shape_key(rowq[row_base + rowf_row(F)]);
             for (int k = 0; k < kShapeSlots; ++k)
                 if (slot[k] == key) {
                     sh = (uint32_t)k + 1u;
                     break;
                 }
         }
-        F.shape = sh;
-        row_shape[row_base + F.row] = sh;
+        F.rs = (F.rs & ~31u) | sh;
+        row_shape[row_base + rowf_row(F)] = sh;
     }
 }
 
@@ -1576,17 +1588,22 @@ __global__ __launch_bounds__(2 * kShapeK) void k_shape_tables(const unsigned lon
     const double b = (double)__uint_as_float((uint32_t)key);
     const double lnb = lgamma(a) + lgamma(b) - lgamma(a + b);
     const int upper = threadIdx.x / kShapeK, k = threadIdx.x % kShapeK;
-    tab[(size_t)blockIdx.x * 2 * kShapeK + threadIdx.x] = shape_table_logit(a, b, lnb, upper, k);
+    float *slot = tab + (size_t)blockIdx.x * kShapeStride;
+    slot[threadIdx.x] = shape_table_logit(a, b, lnb, upper, k);
+    // the Beta parameters of the slot's rows, as the row fit computes them
+    if (threadIdx.x == 0)
+        *reinterpret_cast<float4 *>(slot + 2 * kShapeK) =
+            make_float4((float)a, (float)b, (float)(lnb * 1.4426950408889634), 0.0f);
 }
 
-hipError_t launch_shape_collect(RowF *rowf, int64_t row_base, int64_t n_rows,
+hipError_t launch_shape_collect(RowF *rowf, const RowQ *rowq, int64_t row_base, int64_t n_rows,
                                 const uint32_t *liveoff, int32_t n_cat, uint32_t *row_shape,
                                 unsigned long long *keys, hipStream_t s) {
-    hipLaunchKernelGGL(k_shape_collect, dim3(1), dim3(256), 0, s, rowf, row_base, liveoff, n_cat,
-                       keys);
+    hipLaunchKernelGGL(k_shape_collect, dim3(1), dim3(256), 0, s, rowf, rowq, row_base, liveoff,
+                       n_cat, keys);
     // a grid over the layer's rows (the paying ones are a prefix of them)
     hipLaunchKernelGGL(k_shape_assign, dim3(grid_for(n_rows > 0 ? n_rows : 1, 256, 1024)),
-                       dim3(256), 0, s, rowf, row_base, liveoff, n_cat, keys, row_shape);
+                       dim3(256), 0, s, rowf, rowq, row_base, liveoff, n_cat, keys, row_shape);
     return hipGetLastError();
 }
 

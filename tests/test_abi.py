@@ -61,6 +61,21 @@ def test_invalid_descriptions_rejected_without_gpu():
     assert ei.value.code == A.ARA_E_INVALID_ARG
 
 
+def test_layer_row_limit_rejected_without_gpu():
+    """A layer's compact row records hold its row index in 27 bits: a layer
+    of 2^27 rows or more is refused before any row is read (the row arrays
+    are not touched, so their true length does not matter here)."""
+    w = config_small(n_trials=10)
+    d = A._Desc(w.portfolio)
+    elts = d.elt_arrays[0]
+    elts[0].n_rows = (1 << 27) - sum(elts[j].n_rows for j in range(1, len(w.portfolio.layers[0].elts)))
+    with pytest.raises(A.AraError) as ei:
+        A.ara_portfolio_workspace_size(d.desc, w.yet.n_catalogue)
+    assert ei.value.code == A.ARA_E_UNSUPPORTED
+    elts[0].n_rows -= 1                       # 2^27 - 1 rows: accepted
+    assert A.ara_portfolio_workspace_size(d.desc, w.yet.n_catalogue) > 0
+
+
 def test_scratch_sizes():
     assert A.ara_run_scratch_size(1_000_000) >= 4_000_000
     assert A.ara_pml_tvar_scratch_size(10) > 0
