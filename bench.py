@@ -75,10 +75,10 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 #    for an elementwise kernel that reads and writes 1 GiB (FETCH 2.0,
 #    WRITE 1.0).
 PROFILED = {
-    "sources_sha256": "81cf698d181e13cec63897c1b1034124f1129220a71f56c8484a189841714006",
+    "sources_sha256": "5b33c6d22be38d8a2aa2655bdb6200c3fe8cce3fdbcded3ac6b52e3e3ef18298",
     "draw_arith_ops": 207.0,        # profiles/ara_su_full_counters.md (k_probe_draws)
-    "su_main_bytes": 2.7378e10 + 1.0429e8,   # k_ara_su: fetch + write, 1M trials
-    "pu_bytes": 4.0932e9 + 9.685e6,          # k_ara_pu: fetch + write, 1M trials
+    "su_main_bytes": 4.4169e9 + 1.2172e8,    # k_ara_su: fetch + write, 1M trials
+    "pu_bytes": 4.0934e9 + 9.714e6,          # k_ara_pu: fetch + write, 1M trials
 }
 
 
