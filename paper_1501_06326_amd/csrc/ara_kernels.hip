@@ -20,7 +20,9 @@
 //        "convergence switching" idea applied to SIMD lanes).  A trial with
 //        a hit that needs the FP64 quantile (tail band, shapes outside the
 //        FP32 domain, the two-normal mix, FP32 non-convergence) is handed to
-//        k_ara_su_redo, which runs it again with the FP64 path in place.
+//        k_ara_su_redo, which runs it again with the FP64 path in place
+//        (k_ara_su_redo4: the same code in a 4-wavefront register budget,
+//        for portfolios with FP64-quantile rows and no mixed rows).
 //      - k_ara_batch / k_ara_batch_items: the same trial code over
 //        (portfolio, trial tile) work items of many portfolios at once.
 //      - the occurrence view (per-occurrence increments of the aggregate
